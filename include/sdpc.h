@@ -1,0 +1,228 @@
+/*
+ * sdpc.h -- C ABI of the matrix-completion primal-dual interior-point hot
+ * path on one AMD MI355X (gfx950).
+ *
+ * Problem (Section 1 of Yamashita & Nakata, "Fast implementation for
+ * semidefinite programs with positive matrix completion"):
+ *
+ *   (P)  min A_0 . X   s.t.  A_k . X = b_k (k = 1..m),  X psd
+ *   (D)  max sum_k b_k z_k   s.t.  sum_k A_k z_k + Y = A_0,  Y psd
+ *
+ * The primal matrix is kept only on the extended sparsity pattern E (the
+ * chordal extension of the aggregate pattern, Section 2.1); its
+ * max-determinant completion X^ is applied through the Cholesky factor of
+ * its inverse, X^{-1} = Lhat Lhat^T, built clique by clique (Algorithm 1),
+ * and Y through its sparse Cholesky factor Y = N N^T.  Both factors share
+ * one storage layout (Section 3.1).  The Schur complement matrix
+ * B_pq = A_p . (X^ A_q Y^{-1}) (eq. SCM, evaluated as in eq. newSCM2) is
+ * assembled on the device and factorised densely in FP64.
+ *
+ * Conventions for every call:
+ *   - All functions return an sdpc_status (0 = SDPC_OK, negative = error);
+ *     nothing throws across the ABI and the library never aborts.  On error
+ *     a detail string is kept on the handle (sdpc_last_error).
+ *   - "Device" pointers are HIP device allocations owned by the caller
+ *     (e.g. torch tensors); "host" pointers are ordinary host memory.
+ *   - All device work is enqueued on the hipStream_t given at create.
+ *     Calls marked (async) return before the work is done; the others
+ *     synchronise that stream before returning.
+ *   - The library allocates all of its device workspace in sdpc_create and
+ *     frees it in sdpc_destroy; no call allocates in between.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - "E-vectors" hold a symmetric matrix on E in the library's storage
+ *     order (sdpc_get_pattern reports, for every stored position, its row
+ *     and column in ORIGINAL indices, or -1 for padding).  Padding slots
+ *     are ignored on input and written as zero on output.
+ */
+#ifndef SDPC_H
+#define SDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdpc_handle sdpc_handle;
+
+typedef enum {
+    SDPC_OK = 0,
+    SDPC_E_ARG = -1,        /* invalid argument (null pointer, bad size, bad index)      */
+    SDPC_E_PATTERN = -2,    /* structure not supported (e.g. a clique larger than 64)    */
+    SDPC_E_NOT_PD = -3,     /* a matrix that must be positive definite is not            */
+    SDPC_E_HIP = -4,        /* a HIP runtime call failed                                 */
+    SDPC_E_MAXITER = -5,    /* iteration limit reached before the stopping test held     */
+    SDPC_E_STAGNATION = -6, /* step lengths collapsed; no further progress               */
+    SDPC_E_NUMERIC = -7,    /* NaN or Inf met                                            */
+    SDPC_E_OOM = -8         /* device allocation failed at create                        */
+} sdpc_status;
+
+/* The problem in standard form.  Host memory, read only during sdpc_create.
+ * Matrix A_k (k = 0..m) is the list of lower-triangle triplets
+ * (row[t], col[t], val[t]) for t in [ptr[k], ptr[k+1]); indices are 0-based
+ * with row >= col; duplicates are summed; the upper triangle is implied by
+ * symmetry. */
+typedef struct {
+    int32_t n;                 /* order of X and Y                        */
+    int32_t m;                 /* number of constraints                   */
+    const int64_t *ptr;        /* m + 2 offsets                           */
+    const int32_t *row;
+    const int32_t *col;
+    const double *val;
+    const double *b;           /* length m                                */
+} sdpc_problem;
+
+/* Parameters.  The paper leaves beta, gamma, the initial point and the
+ * stopping rule open (Section 2.2); the defaults are the readings the CPU
+ * oracle uses as well. */
+typedef struct {
+    double gap_tol;            /* relative gap  |P-D| / max(1,(|P|+|D|)/2)         (1e-7)  */
+    double feas_tol;           /* primal / dual infeasibility tolerance            (1e-7)  */
+    double beta_feas;          /* centring parameter once feasible                 (0.1)   */
+    double beta_infeas;        /* centring parameter before                        (0.2)   */
+    double gamma;              /* fraction of the maximal step                     (0.9)   */
+    double lambda0;            /* X0 = Y0 = lambda0 I, z0 = 0                      (100)   */
+    int32_t max_iter;          /*                                                  (100)   */
+    int32_t ordering;          /* 0 natural, 1 minimum degree, 2 user_perm         (0)     */
+    int32_t block_width;       /* widest storage block (columns), 1..32            (32)    */
+    int32_t verbose;           /* 1: one line per iteration on stderr              (0)     */
+    const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
+                                  i-th (host, read at create)                              */
+} sdpc_params;
+
+/* Result of sdpc_solve / sdpc_step. */
+typedef struct {
+    int32_t status;            /* sdpc_status of the solve                                 */
+    int32_t iters;             /* iterations performed                                     */
+    double pobj, dobj;         /* A_0 . X and b . z                                        */
+    double rel_gap, pinf, dinf;
+    double mu, alpha_p, alpha_d, beta;   /* last iteration                                 */
+    double t_scm_ms;           /* device time: Y factor, Algorithm 1, solves, SCM (sum)    */
+    double t_chol_ms;          /* device time: SCM Cholesky and SCE solve (sum)            */
+    double t_pmatrix_ms;       /* device time: dX on E and the step lengths (sum)          */
+    double t_total_ms;         /* wall time of the call                                    */
+    size_t device_bytes;       /* device workspace held by the handle                      */
+} sdpc_result;
+
+/* Defaults listed above. */
+sdpc_params sdpc_default_params(void);
+
+/* Sizes found by the symbolic phase. */
+typedef struct {
+    int64_t nslot;             /* stored positions of the shared factor layout            */
+    int64_t nnzE;              /* lower-triangle entries of E (diagonal included)          */
+    int32_t ncliques;          /* l, the number of cliques (supernodes)                    */
+    int32_t nblocks;           /* storage blocks                                           */
+    int32_t max_clique;        /* max |C_r|                                                */
+    int32_t max_block_rows, max_block_cols;
+    int32_t nfwd, nbwd;        /* live rows of the forward / backward substitutions         */
+    int32_t hadamard;          /* 1 when every A_k (k >= 1) is one diagonal entry          */
+    int64_t sum_clique;        /* sum_r |C_r|                                              */
+} sdpc_analysis;
+
+/* Host-only symbolic phase (Section 2.1, Section 3.1); touches no device
+ * and may run on a machine without a GPU.  info (host) receives the sizes.
+ * Optional host outputs (NULL to skip): perm (n): elimination order,
+ * perm[i] = original index eliminated i-th; cptr (ncliques + 1), cidx
+ * (sum_clique), nS (ncliques): the cliques C_r in original indices, S_r
+ * being the first nS[r] members.  Call once with NULL arrays to size them. */
+sdpc_status sdpc_analyze(const sdpc_problem *prob, const sdpc_params *params, sdpc_analysis *info,
+                         int32_t *perm, int64_t *cptr, int32_t *cidx, int32_t *nS);
+
+/* Symbolic phase (Section 2.1, Section 3.1): aggregate pattern, ordering,
+ * chordal extension, elimination tree, supernodes as the clique sequence
+ * C_1..C_l with S_r / U_r, storage blocks, all index maps; then allocates
+ * the device workspace and uploads the problem.  params may be NULL
+ * (defaults).  On success *out owns everything; on failure *out is NULL. */
+sdpc_status sdpc_create(const sdpc_problem *prob, const sdpc_params *params,
+                        hipStream_t stream, sdpc_handle **out);
+
+/* Full solve from the initial point of Section 2.2, Step 0, to the stopping
+ * test (Steps 1-4 repeated).  res (host) receives the outcome.  The final
+ * iterate stays on the handle (sdpc_get_solution). */
+sdpc_status sdpc_solve(sdpc_handle *h, sdpc_result *res);
+
+/* Reset the iterate to Step 0's initial point. (async) */
+sdpc_status sdpc_reset(sdpc_handle *h);
+
+/* One iteration (Steps 1-4) from the handle's current iterate.  Returns
+ * SDPC_OK after an update; res->status is SDPC_OK when the stopping test
+ * already held (no update made). */
+sdpc_status sdpc_step(sdpc_handle *h, sdpc_result *res);
+
+/* The Schur complement matrix at a given state: Y = N N^T (sparse
+ * Cholesky), Lhat by Algorithm 1 from Xbar, the columns of X^ and Y^{-1}
+ * by sparse substitutions, then B_pq = A_p . (X^ A_q Y^{-1}) (eq. SCM /
+ * eq. newSCM2).  d_Xbar_E, d_Y_E: E-vectors (device, length nslot).  d_B:
+ * device m x m column-major, leading dimension ldb >= m; the lower triangle
+ * (row >= col, constraint order) is written, the strict upper triangle is
+ * left untouched.  factor != 0 additionally overwrites that lower triangle
+ * with the Cholesky factor R of B (B = R R^T).  Errors found on the device
+ * (a non-positive-definite clique block of Xbar, a Y that is not positive
+ * definite, a B that is not) are reported by the return value, so the call
+ * synchronises the stream before returning. */
+sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E,
+                     double *d_B, int64_t ldb, int32_t factor);
+
+/* Dense FP64 Cholesky B = R R^T in place (lower triangle of a column-major
+ * m x m device matrix, ldb >= m), the factorisation used for the SCM
+ * (type (i) of Section 3.1).  The strict upper triangle is not referenced.
+ * Returns SDPC_E_NOT_PD (with the pivot in the detail string) if B is not
+ * positive definite.  Synchronises. */
+sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m);
+
+/* Pattern of the storage layout.  *nslot receives the number of stored
+ * positions.  iE / jE (host, length nslot, may be NULL) receive, for each
+ * stored position, its (row, col) in ORIGINAL indices with row >= col in the
+ * elimination order's sense (the position's own row/column), or -1/-1 for a
+ * padding slot outside E.  perm (host, length n, may be NULL) receives the
+ * elimination order: perm[i] = original index eliminated i-th.  ncliques
+ * (may be NULL) receives the number of cliques (supernodes) l. */
+sdpc_status sdpc_get_pattern(const sdpc_handle *h, int64_t *nslot, int32_t *iE, int32_t *jE,
+                             int32_t *perm, int32_t *ncliques);
+
+/* Clique sequence C_1..C_l (original indices): cptr (host, l + 1) and cidx
+ * (host, sum |C_r|), with S_r the first nS[r] members of C_r.  Any array may
+ * be NULL. */
+sdpc_status sdpc_get_cliques(const sdpc_handle *h, int64_t *cptr, int32_t *cidx, int32_t *nS);
+
+/* Current iterate: Xbar_E, Y_E (E-vectors) and z (length m); device
+ * pointers, any may be NULL.  Synchronises. */
+sdpc_status sdpc_get_solution(const sdpc_handle *h, double *d_Xbar_E, double *d_Y_E, double *d_z);
+
+/* Replace the current iterate (device pointers; none may be NULL). (async) */
+sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E,
+                           const double *d_z);
+
+/* Factors of the last sdpc_scm / iteration in the storage layout (E-vectors
+ * in the elimination order): d_N (Y = N N^T), d_Lhat (X^{-1} = Lhat Lhat^T).
+ * Either may be NULL.  Synchronises. */
+sdpc_status sdpc_get_factors(const sdpc_handle *h, double *d_N, double *d_Lhat);
+
+/* Dense X^ (max-determinant completion, Section 2.1) and Y^{-1} of the
+ * last sdpc_scm / iteration, n x n column-major in the ELIMINATION order
+ * (position i is original index perm[i]).  Either may be NULL.  Synchronises. */
+sdpc_status sdpc_get_dense(const sdpc_handle *h, double *d_Xhat, double *d_Yinv);
+
+/* Search direction of the last sdpc_step (Section 2.2, Step 2 with
+ * eq. newdX2 and the clique-wise step of eq. primal_length2): d_dz (length
+ * m), d_dX_E, d_dY_E (E-vectors), and the host scalars alpha (2 doubles:
+ * alpha_p, alpha_d before the gamma factor).  Any may be NULL.  Synchronises. */
+sdpc_status sdpc_get_direction(const sdpc_handle *h, double *d_dz, double *d_dX_E,
+                               double *d_dY_E, double *alpha);
+
+/* Device time (ms) of the kernels of the last sdpc_scm, split as
+ * [Y factor, Algorithm 1, solves, SCM assembly, SCM Cholesky].  Host array
+ * of 5.  Synchronises. */
+sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5);
+
+const char *sdpc_status_string(sdpc_status s);
+const char *sdpc_last_error(const sdpc_handle *h);
+void sdpc_destroy(sdpc_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDPC_H */

@@ -1,0 +1,940 @@
+// C ABI of the matrix-completion PDIPM hot path (see include/sdpc.h).
+//
+// sdpc_create  host symbolic phase (symbolic.cpp) + every index map the
+//              kernels need, then one upload; all device workspace is
+//              allocated here and nowhere else.
+// scm phase    Y = N N^T, Lhat by Algorithm 1, X^ = Lhat^{-T} Lhat^{-1} and
+//              Y^{-1} = N^{-T} N^{-1} column by column, B (eq. SCM / newSCM2),
+//              optional Cholesky of B.
+// sdpc_step    Section 2.2, Steps 1-4: stopping test, HKM direction (SCE,
+//              dY, dX on E by eq. newdX2), step lengths (eq. primal_length2
+//              clique by clique; the dual one by a parallel positive-
+//              definiteness test of Y + alpha dY on many alphas at once),
+//              update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sdpc.h"
+#include "kernels.h"
+#include "symbolic.h"
+
+using namespace sdpc;
+
+namespace {
+
+constexpr int kCand = 64;        // dual step-length candidates per round
+constexpr int kDualRounds = 6;   // log grid, then five even refinements: ~3e-10 relative
+
+struct Timer {
+    hipEvent_t a{}, b{};
+};
+
+}  // namespace
+
+struct sdpc_handle {
+    hipStream_t st = nullptr;
+    int n = 0, m = 0;
+    sdpc_params prm{};
+    Symbolic S;
+    SolveSlots slots;
+    DevStruct d;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    std::string err;
+    // host mirrors
+    std::vector<int64_t> kq_ptr_h;
+    double bmax = 0.0, a0max = 0.0;
+    std::vector<int> slot_row_h, slot_col_h;
+    // state (E-vectors unless noted)
+    double *X = nullptr, *Y = nullptr, *z = nullptr, *G = nullptr;
+    double *dX = nullptr, *dY = nullptr, *dz = nullptr;
+    double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
+    double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
+    double *B = nullptr, *g = nullptr, *hcol = nullptr, *pwork = nullptr, *ty = nullptr;
+    double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr;
+    int *flags = nullptr;   // [0..kCand) sn_chol, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2] potrf
+    int64_t ldb = 0;
+    double last_alpha[2] = {0, 0};
+    double scm_ms[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[8]{};
+    int iters = 0;
+};
+
+namespace {
+
+sdpc_status fail(sdpc_handle *h, sdpc_status s, const std::string &msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+#define HIPCHK(h, call)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(h, SDPC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+template <class Tp>
+sdpc_status dalloc(sdpc_handle *h, Tp **p, size_t count) {
+    void *q = nullptr;
+    const size_t nbytes = std::max<size_t>(count, 1) * sizeof(Tp);
+    if (hipMalloc(&q, nbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, SDPC_E_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+    }
+    h->allocs.push_back(q);
+    h->bytes += nbytes;
+    *p = static_cast<Tp *>(q);
+    return SDPC_OK;
+}
+
+template <class Tp>
+sdpc_status upload(sdpc_handle *h, const Tp **dst, const std::vector<Tp> &src) {
+    Tp *p = nullptr;
+    sdpc_status s = dalloc(h, &p, src.size());
+    if (s != SDPC_OK) return s;
+    if (!src.empty()) HIPCHK(h, hipMemcpyAsync(p, src.data(), src.size() * sizeof(Tp), hipMemcpyHostToDevice, h->st));
+    *dst = p;
+    return SDPC_OK;
+}
+
+#define TRY(x)                              \
+    do {                                    \
+        sdpc_status s_ = (x);               \
+        if (s_ != SDPC_OK) return s_;       \
+    } while (0)
+
+struct Entry {
+    int pi, pj;   // positions, pi >= pj
+    double v;
+};
+
+}  // namespace
+
+extern "C" {
+
+sdpc_params sdpc_default_params(void) {
+    sdpc_params p;
+    p.gap_tol = 1e-7;
+    p.feas_tol = 1e-7;
+    p.beta_feas = 0.1;
+    p.beta_infeas = 0.2;
+    p.gamma = 0.9;
+    p.lambda0 = 100.0;
+    p.max_iter = 100;
+    p.ordering = 0;
+    p.block_width = 32;
+    p.verbose = 0;
+    p.user_perm = nullptr;
+    return p;
+}
+
+const char *sdpc_status_string(sdpc_status s) {
+    switch (s) {
+        case SDPC_OK: return "ok";
+        case SDPC_E_ARG: return "invalid argument";
+        case SDPC_E_PATTERN: return "unsupported structure";
+        case SDPC_E_NOT_PD: return "matrix not positive definite";
+        case SDPC_E_HIP: return "HIP runtime error";
+        case SDPC_E_MAXITER: return "iteration limit reached";
+        case SDPC_E_STAGNATION: return "stagnation";
+        case SDPC_E_NUMERIC: return "non-finite values";
+        case SDPC_E_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char *sdpc_last_error(const sdpc_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+void sdpc_destroy(sdpc_handle *h) {
+    if (!h) return;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    for (void *p : h->allocs) (void)hipFree(p);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete h;
+}
+
+static sdpc_status check_problem(const sdpc_problem *prob, sdpc_handle *h) {
+    const int n = prob->n, m = prob->m;
+    if (h->prm.block_width < 1 || h->prm.block_width > 32) return fail(h, SDPC_E_ARG, "block_width must be 1..32");
+    if (h->prm.gamma <= 0 || h->prm.gamma >= 1) return fail(h, SDPC_E_ARG, "gamma must be in (0,1)");
+    const int64_t nnz = prob->ptr[m + 1];
+    if (prob->ptr[0] != 0 || nnz < 0) return fail(h, SDPC_E_ARG, "ptr must start at 0");
+    for (int k = 0; k <= m; ++k)
+        if (prob->ptr[k + 1] < prob->ptr[k]) return fail(h, SDPC_E_ARG, "ptr not monotone");
+    for (int64_t t = 0; t < nnz; ++t) {
+        const int r = prob->row[t], c = prob->col[t];
+        if (r < 0 || r >= n || c < 0 || c >= n || r < c)
+            return fail(h, SDPC_E_ARG, "entry " + std::to_string(t) + " is not a lower-triangle index");
+        if (!std::isfinite(prob->val[t])) return fail(h, SDPC_E_ARG, "non-finite value in A");
+    }
+    for (int k = 0; k < m; ++k)
+        if (!std::isfinite(prob->b[k])) return fail(h, SDPC_E_ARG, "non-finite b");
+    return SDPC_OK;
+}
+
+// lower-triangle aggregate pattern (original indices, diagonal included), then the symbolic phase
+static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::vector<int> &arow,
+                                std::vector<int> &acol) {
+    const int n = prob->n, m = prob->m;
+    const int64_t nnz = prob->ptr[m + 1];
+    {
+        std::vector<std::pair<int, int>> e;
+        e.reserve(size_t(nnz) + n);
+        for (int i = 0; i < n; ++i) e.push_back({i, i});
+        for (int64_t t = 0; t < nnz; ++t) e.push_back({prob->row[t], prob->col[t]});
+        std::sort(e.begin(), e.end());
+        e.erase(std::unique(e.begin(), e.end()), e.end());
+        for (auto &p : e) {
+            arow.push_back(p.first);
+            acol.push_back(p.second);
+        }
+    }
+    SymbolicOptions so;
+    so.ordering = h->prm.ordering;
+    so.user_perm = h->prm.user_perm;
+    so.block_width = h->prm.block_width;
+    so.max_block_entries = 4096;
+    const std::string serr = build_symbolic(n, arow, acol, so, h->S);
+    if (!serr.empty()) return fail(h, SDPC_E_PATTERN, serr);
+    const Symbolic &S = h->S;
+    if (S.max_clique > 64)
+        return fail(h, SDPC_E_PATTERN, "largest clique has " + std::to_string(S.max_clique) + " members (limit 64)");
+    if (S.nslot >= (int64_t(1) << 31)) return fail(h, SDPC_E_PATTERN, "storage exceeds 2^31 entries");
+    h->slots = build_solve_slots(S);
+    h->d.n = n;
+    h->d.nfwd = h->slots.nfwd;
+    h->d.nbwd = h->slots.nbwd;
+    h->d.max_h = S.max_h;
+    h->d.max_w = S.max_w;
+    if (solve_tile_width(h->d) == 0)
+        return fail(h, SDPC_E_PATTERN, "substitution frontier too wide for LDS (" + std::to_string(h->d.nfwd) + "+" +
+                                           std::to_string(h->d.nbwd) + " live rows)");
+    return SDPC_OK;
+}
+
+static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *params, hipStream_t stream,
+                               sdpc_handle *h) {
+    const int n = prob->n, m = prob->m;
+    h->st = stream;
+    h->n = n;
+    h->m = m;
+    h->prm = params ? *params : sdpc_default_params();
+    TRY(check_problem(prob, h));
+    std::vector<int> arow, acol;
+    TRY(analyze_impl(prob, h, arow, acol));
+    const Symbolic &S = h->S;
+    DevStruct &d = h->d;
+    d.n = n;
+    d.m = m;
+    d.nb = S.nb;
+    d.ncl = S.ncl;
+    d.nslot = S.nslot;
+    d.max_h = S.max_h;
+    d.max_w = S.max_w;
+    d.max_clique = S.max_clique;
+    for (int b = 0; b < S.nb; ++b)
+        d.max_panel = std::max<int64_t>(d.max_panel, (S.bl_rptr[b + 1] - S.bl_rptr[b]) *
+                                                         int64_t(S.bl_first[b + 1] - S.bl_first[b]));
+    if (m > 65535) return fail(h, SDPC_E_PATTERN, "more than 65535 constraints");
+    // ---- block arrays
+    std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size());
+    for (size_t t = 0; t < S.bl_rows.size(); ++t) {
+        fs[t] = h->slots.fwd[S.bl_rows[t]];
+        bs[t] = h->slots.bwd[S.bl_rows[t]];
+    }
+    for (int b = 0; b < S.nb; ++b) {
+        const int w = S.bl_first[b + 1] - S.bl_first[b];
+        for (int64_t t = S.bl_rptr[b] + w; t < S.bl_rptr[b + 1]; ++t)
+            if (fs[t] < 0 || bs[t] < 0) return fail(h, SDPC_E_PATTERN, "internal: solve slot missing");
+    }
+    std::vector<int64_t> dinv_off(S.nb + 1, 0), up_ptr(S.nb + 1, 0);
+    std::vector<int> up_pair, up_slot;
+    for (int b = 0; b < S.nb; ++b) {
+        const int F = S.bl_first[b], w = S.bl_first[b + 1] - F;
+        const int64_t r0 = S.bl_rptr[b];
+        const int hp = int(S.bl_rptr[b + 1] - r0) - w;
+        dinv_off[b + 1] = dinv_off[b] + int64_t(w) * w;
+        for (int c = 0; c < hp; ++c)
+            for (int a = c; a < hp; ++a) {
+                up_pair.push_back(a | (c << 16));
+                up_slot.push_back(int(S.slot(S.bl_rows[r0 + w + a], S.bl_rows[r0 + w + c])));
+            }
+        up_ptr[b + 1] = int64_t(up_pair.size());
+    }
+    // ---- cliques
+    std::vector<int64_t> cl_ptr(S.ncl + 1, 0), cl_map_ptr(S.ncl + 1, 0);
+    std::vector<int> cl_rows, cl_map;
+    for (int r = 0; r < S.ncl; ++r) {
+        const int f = S.cl_first[r];
+        const int64_t s0 = S.sptr[f], s1 = S.sptr[f + 1];
+        const int c = int(s1 - s0);
+        for (int64_t t = s0; t < s1; ++t) cl_rows.push_back(S.sidx[t]);
+        for (int jj = 0; jj < c; ++jj)
+            for (int ii = jj; ii < c; ++ii) {
+                const int64_t sl = S.slot(S.sidx[s0 + ii], S.sidx[s0 + jj]);
+                if (sl < 0) return fail(h, SDPC_E_PATTERN, "internal: clique entry not stored");
+                cl_map.push_back(int(sl));
+            }
+        cl_ptr[r + 1] = int64_t(cl_rows.size());
+        cl_map_ptr[r + 1] = int64_t(cl_map.size());
+    }
+    // ---- per-slot row/col and weights
+    std::vector<int> slot_row(S.nslot, -1), slot_col(S.nslot, -1);
+    std::vector<double> wE(S.nslot, 0.0);
+    for (int b = 0; b < S.nb; ++b) {
+        const int F = S.bl_first[b], w = S.bl_first[b + 1] - F;
+        const int64_t r0 = S.bl_rptr[b];
+        const int hh = int(S.bl_rptr[b + 1] - r0);
+        for (int c = 0; c < w; ++c)
+            for (int p = 0; p < hh; ++p) {
+                const int64_t s = S.bl_off[b] + p + int64_t(hh) * c;
+                if (!S.isE[s]) continue;
+                slot_row[s] = S.bl_rows[r0 + p];
+                slot_col[s] = F + c;
+                wE[s] = (slot_row[s] == slot_col[s]) ? 1.0 : 2.0;
+            }
+    }
+    h->slot_row_h = slot_row;
+    h->slot_col_h = slot_col;
+    // ---- problem entries in positions
+    std::vector<std::vector<Entry>> ent(m + 1);
+    for (int k = 0; k <= m; ++k)
+        for (int64_t t = prob->ptr[k]; t < prob->ptr[k + 1]; ++t) {
+            int a = S.pos[prob->row[t]], c = S.pos[prob->col[t]];
+            if (a < c) std::swap(a, c);
+            if (prob->val[t] != 0.0) ent[k].push_back({a, c, prob->val[t]});
+        }
+    h->a0max = 0.0;
+    for (auto &e : ent[0]) h->a0max = std::max(h->a0max, std::fabs(e.v));
+    h->bmax = 0.0;
+    for (int k = 0; k < m; ++k) h->bmax = std::max(h->bmax, std::fabs(prob->b[k]));
+    // assembly by slot
+    std::vector<int64_t> asm_ptr(S.nslot + 1, 0);
+    std::vector<int> asm_k;
+    std::vector<double> asm_val;
+    {
+        std::vector<std::pair<int64_t, std::pair<int, double>>> tmp;
+        for (int k = 0; k <= m; ++k)
+            for (auto &e : ent[k]) tmp.push_back({S.slot(e.pi, e.pj), {k, e.v}});
+        std::stable_sort(tmp.begin(), tmp.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (auto &t : tmp) {
+            if (t.first < 0) return fail(h, SDPC_E_PATTERN, "internal: aggregate entry not stored");
+            asm_ptr[t.first + 1]++;
+            asm_k.push_back(t.second.first);
+            asm_val.push_back(t.second.second);
+        }
+        for (int64_t s = 0; s < S.nslot; ++s) asm_ptr[s + 1] += asm_ptr[s];
+    }
+    // constraints by k
+    std::vector<int64_t> con_ptr(m + 2, 0);
+    std::vector<int> con_pi, con_pj, con_slot;
+    std::vector<double> con_val;
+    for (int k = 0; k <= m; ++k) {
+        for (auto &e : ent[k]) {
+            con_pi.push_back(e.pi);
+            con_pj.push_back(e.pj);
+            con_slot.push_back(int(S.slot(e.pi, e.pj)));
+            con_val.push_back(e.v * (e.pi == e.pj ? 1.0 : 2.0));
+        }
+        con_ptr[k + 1] = int64_t(con_pi.size());
+    }
+    // Hadamard form: every A_k (k >= 1) a single diagonal position
+    bool had = m > 0;
+    std::vector<int> had_pos(m, 0);
+    std::vector<double> had_val(m, 0.0);
+    for (int k = 1; k <= m && had; ++k) {
+        if (ent[k].empty()) { had = false; break; }
+        const int p0 = ent[k][0].pi;
+        double v = 0.0;
+        for (auto &e : ent[k]) {
+            if (e.pi != p0 || e.pj != p0) { had = false; break; }
+            v += e.v;
+        }
+        had_pos[k - 1] = p0;
+        had_val[k - 1] = v;
+    }
+    d.hadamard = had ? 1 : 0;
+    // general path: A_q full symmetric CSC over its nonzero columns; union support by rows
+    std::vector<int64_t> kq_ptr(m + 1, 0), aq_cptr(1, 0);
+    std::vector<int> kq_col, aq_row;
+    std::vector<double> aq_val;
+    std::map<std::pair<int, int>, int64_t> sup;   // (row, col) -> support index
+    for (int q = 1; q <= m; ++q) {
+        std::vector<std::pair<std::pair<int, int>, double>> full;   // ((col, row), v)
+        for (auto &e : ent[q]) {
+            full.push_back({{e.pj, e.pi}, e.v});
+            if (e.pi != e.pj) full.push_back({{e.pi, e.pj}, e.v});
+        }
+        std::sort(full.begin(), full.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        int lastc = -1;
+        for (auto &f : full) {
+            const int col = f.first.first, row = f.first.second;
+            if (col != lastc) {
+                kq_col.push_back(col);
+                aq_cptr.push_back(aq_cptr.back());
+                lastc = col;
+            }
+            aq_row.push_back(row);
+            aq_val.push_back(f.second);
+            aq_cptr.back()++;
+            sup.emplace(std::make_pair(row, col), 0);
+        }
+        kq_ptr[q] = int64_t(kq_col.size());
+    }
+    std::vector<int64_t> S_rowptr(n + 1, 0);
+    std::vector<int> S_col;
+    {
+        int64_t idx = 0;
+        for (auto &kv : sup) {
+            kv.second = idx++;
+            S_rowptr[kv.first.first + 1]++;
+            S_col.push_back(kv.first.second);
+        }
+        for (int i = 0; i < n; ++i) S_rowptr[i + 1] += S_rowptr[i];
+    }
+    std::vector<int64_t> am_ptr(m + 1, 0), am_sidx;
+    std::vector<double> am_val;
+    for (int q = 1; q <= m; ++q) {
+        for (auto &e : ent[q]) {
+            am_sidx.push_back(sup[{e.pi, e.pj}]);
+            am_val.push_back(e.v);
+            if (e.pi != e.pj) {
+                am_sidx.push_back(sup[{e.pj, e.pi}]);
+                am_val.push_back(e.v);
+            }
+        }
+        am_ptr[q] = int64_t(am_sidx.size());
+    }
+    h->kq_ptr_h = kq_ptr;
+    // aggregate pattern, full symmetric CSC with slots
+    std::vector<int64_t> ag_cptr(n + 1, 0);
+    std::vector<int> ag_row, ag_slot;
+    {
+        std::vector<std::vector<std::pair<int, int>>> cols(n);
+        for (size_t t = 0; t < arow.size(); ++t) {
+            int a = S.pos[arow[t]], c = S.pos[acol[t]];
+            if (a < c) std::swap(a, c);
+            const int sl = int(S.slot(a, c));
+            cols[c].push_back({a, sl});
+            if (a != c) cols[a].push_back({c, sl});
+        }
+        for (int j = 0; j < n; ++j) {
+            std::sort(cols[j].begin(), cols[j].end());
+            for (auto &p : cols[j]) {
+                ag_row.push_back(p.first);
+                ag_slot.push_back(p.second);
+            }
+            ag_cptr[j + 1] = int64_t(ag_row.size());
+        }
+    }
+    // ---- uploads
+    TRY(upload(h, &d.bl_first, S.bl_first));
+    TRY(upload(h, &d.bl_rptr, S.bl_rptr));
+    TRY(upload(h, &d.bl_rows, S.bl_rows));
+    TRY(upload(h, &d.bl_off, S.bl_off));
+    TRY(upload(h, &d.bl_subfirst, S.bl_subfirst));
+    TRY(upload(h, &d.bl_fslot, fs));
+    TRY(upload(h, &d.bl_bslot, bs));
+    TRY(upload(h, &d.bl_dinv, dinv_off));
+    TRY(upload(h, &d.up_ptr, up_ptr));
+    TRY(upload(h, &d.up_pair, up_pair));
+    TRY(upload(h, &d.up_slot, up_slot));
+    TRY(upload(h, &d.col_block, S.col_block));
+    TRY(upload(h, &d.slot_row, slot_row));
+    TRY(upload(h, &d.slot_col, slot_col));
+    TRY(upload(h, &d.cl_first, S.cl_first));
+    TRY(upload(h, &d.cl_ptr, cl_ptr));
+    TRY(upload(h, &d.cl_rows, cl_rows));
+    TRY(upload(h, &d.cl_map_ptr, cl_map_ptr));
+    TRY(upload(h, &d.cl_map, cl_map));
+    TRY(upload(h, &d.wE, wE));
+    TRY(upload(h, &d.asm_ptr, asm_ptr));
+    TRY(upload(h, &d.asm_k, asm_k));
+    TRY(upload(h, &d.asm_val, asm_val));
+    TRY(upload(h, &d.con_ptr, con_ptr));
+    TRY(upload(h, &d.con_pi, con_pi));
+    TRY(upload(h, &d.con_pj, con_pj));
+    TRY(upload(h, &d.con_slot, con_slot));
+    TRY(upload(h, &d.con_val, con_val));
+    std::vector<double> bvec(prob->b, prob->b + m);
+    TRY(upload(h, &d.b, bvec));
+    TRY(upload(h, &d.had_pos, had_pos));
+    TRY(upload(h, &d.had_val, had_val));
+    TRY(upload(h, &d.kq_ptr, kq_ptr));
+    TRY(upload(h, &d.kq_col, kq_col));
+    TRY(upload(h, &d.aq_cptr, aq_cptr));
+    TRY(upload(h, &d.aq_row, aq_row));
+    TRY(upload(h, &d.aq_val, aq_val));
+    d.nS = int64_t(S_col.size());
+    TRY(upload(h, &d.S_rowptr, S_rowptr));
+    TRY(upload(h, &d.S_col, S_col));
+    TRY(upload(h, &d.am_ptr, am_ptr));
+    TRY(upload(h, &d.am_sidx, am_sidx));
+    TRY(upload(h, &d.am_val, am_val));
+    TRY(upload(h, &d.ag_cptr, ag_cptr));
+    TRY(upload(h, &d.ag_row, ag_row));
+    TRY(upload(h, &d.ag_slot, ag_slot));
+    // ---- workspace
+    const size_t ns = size_t(S.nslot), nn = size_t(n) * n;
+    h->ldb = std::max<int64_t>(m, 1);
+    TRY(dalloc(h, &h->X, ns));
+    TRY(dalloc(h, &h->Y, ns));
+    TRY(dalloc(h, &h->G, ns));
+    TRY(dalloc(h, &h->dX, ns));
+    TRY(dalloc(h, &h->dY, ns));
+    TRY(dalloc(h, &h->N, ns));
+    TRY(dalloc(h, &h->Lhat, ns));
+    TRY(dalloc(h, &h->z, size_t(m)));
+    TRY(dalloc(h, &h->dz, size_t(m)));
+    TRY(dalloc(h, &h->g, size_t(m)));
+    TRY(dalloc(h, &h->hcol, size_t(m)));
+    TRY(dalloc(h, &h->ty, size_t(m)));
+    TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
+    TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
+    TRY(dalloc(h, &h->Xh, nn));
+    TRY(dalloc(h, &h->Yi, nn));
+    TRY(dalloc(h, &h->W, nn));
+    TRY(dalloc(h, &h->T, std::max<size_t>(size_t(d.nS), 1)));
+    TRY(dalloc(h, &h->B, size_t(h->ldb) * m));
+    TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
+    TRY(dalloc(h, &h->scal, 16));
+    TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
+    TRY(dalloc(h, &h->alphas, kCand));
+    TRY(dalloc(h, &h->cand, ns * kCand));
+    TRY(dalloc(h, &h->flags, kCand + 8));
+    HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
+    HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
+    HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), h->st));
+    for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
+    launch_init_point(d, h->prm.lambda0, h->X, h->Y, h->z, h->st);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_analyze(const sdpc_problem *prob, const sdpc_params *params, sdpc_analysis *info, int32_t *perm,
+                         int64_t *cptr, int32_t *cidx, int32_t *nS) {
+    if (!prob || !info || !prob->ptr || prob->n <= 0 || prob->m < 0 || (prob->m > 0 && !prob->b)) return SDPC_E_ARG;
+    if (prob->ptr[prob->m + 1] > 0 && (!prob->row || !prob->col || !prob->val)) return SDPC_E_ARG;
+    std::unique_ptr<sdpc_handle> h(new (std::nothrow) sdpc_handle());
+    if (!h) return SDPC_E_OOM;
+    h->n = prob->n;
+    h->m = prob->m;
+    h->prm = params ? *params : sdpc_default_params();
+    sdpc_status s = check_problem(prob, h.get());
+    std::vector<int> arow, acol;
+    if (s == SDPC_OK) s = analyze_impl(prob, h.get(), arow, acol);
+    if (s != SDPC_OK) {
+        if (h->prm.verbose) fprintf(stderr, "sdpc_analyze: %s\n", h->err.c_str());
+        return s;
+    }
+    const Symbolic &S = h->S;
+    std::memset(info, 0, sizeof(*info));
+    info->nslot = S.nslot;
+    for (uint8_t e : S.isE) info->nnzE += e;
+    info->ncliques = S.ncl;
+    info->nblocks = S.nb;
+    info->max_clique = S.max_clique;
+    info->max_block_rows = S.max_h;
+    info->max_block_cols = S.max_w;
+    info->nfwd = h->slots.nfwd;
+    info->nbwd = h->slots.nbwd;
+    bool had = prob->m > 0;
+    for (int k = 1; k <= prob->m && had; ++k) {
+        int p0 = -1;
+        bool any = false;
+        for (int64_t t = prob->ptr[k]; t < prob->ptr[k + 1]; ++t) {
+            if (prob->val[t] == 0.0) continue;
+            if (prob->row[t] != prob->col[t] || (p0 >= 0 && prob->row[t] != p0)) { had = false; break; }
+            p0 = prob->row[t];
+            any = true;
+        }
+        had = had && any;
+    }
+    info->hadamard = had ? 1 : 0;
+    int64_t off = 0;
+    if (cptr) cptr[0] = 0;
+    for (int r = 0; r < S.ncl; ++r) {
+        const int f = S.cl_first[r];
+        for (int64_t t = S.sptr[f]; t < S.sptr[f + 1]; ++t) {
+            if (cidx) cidx[off] = S.perm[S.sidx[t]];
+            ++off;
+        }
+        if (cptr) cptr[r + 1] = off;
+        if (nS) nS[r] = S.cl_first[r + 1] - f;
+    }
+    info->sum_clique = off;
+    if (perm) std::copy(S.perm.begin(), S.perm.end(), perm);
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_create(const sdpc_problem *prob, const sdpc_params *params, hipStream_t stream, sdpc_handle **out) {
+    if (!out) return SDPC_E_ARG;
+    *out = nullptr;
+    if (!prob || !prob->ptr || prob->n <= 0 || prob->m < 0 || (prob->m > 0 && !prob->b)) return SDPC_E_ARG;
+    if (prob->ptr[prob->m + 1] > 0 && (!prob->row || !prob->col || !prob->val)) return SDPC_E_ARG;
+    sdpc_handle *h = new (std::nothrow) sdpc_handle();
+    if (!h) return SDPC_E_OOM;
+    sdpc_status s = create_impl(prob, params, stream, h);
+    if (s != SDPC_OK) {
+        // keep the message reachable for the caller through stderr only; the handle is gone
+        if (h->prm.verbose) fprintf(stderr, "sdpc_create: %s\n", h->err.c_str());
+        sdpc_destroy(h);
+        return s;
+    }
+    *out = h;
+    return SDPC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int read_flag(sdpc_handle *h, int idx) {
+    int v = 0;
+    (void)hipMemcpy(&v, h->flags + idx, sizeof(int), hipMemcpyDeviceToHost);
+    return v;
+}
+
+// Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
+sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, double *B, int64_t ldb, bool factor) {
+    DevStruct &d = h->d;
+    hipStream_t st = h->st;
+    HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
+    HIPCHK(h, hipEventRecord(h->ev[0], st));
+    launch_sn_chol(d, Y, h->N, h->flags, st);
+    launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
+    HIPCHK(h, hipEventRecord(h->ev[1], st));
+    launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
+    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
+    HIPCHK(h, hipEventRecord(h->ev[2], st));
+    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, st);
+    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, st);
+    HIPCHK(h, hipEventRecord(h->ev[3], st));
+    if (d.hadamard)
+        launch_scm_hadamard(d, h->Xh, h->Yi, B, ldb, st);
+    else
+        launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
+    HIPCHK(h, hipEventRecord(h->ev[4], st));
+    if (factor) launch_potrf(d.m, B, ldb, h->pwork, h->flags + kCand + 2, st);
+    HIPCHK(h, hipEventRecord(h->ev[5], st));
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(st));
+    for (int i = 0; i < 5; ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]);
+        h->scm_ms[i] = ms;
+    }
+    int fl[kCand + 8];
+    HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl[0]) return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[0] - 1) + ")");
+    if (fl[kCand + 1])
+        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[kCand + 1] - 1) + ")");
+    if (fl[kCand]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
+    if (factor && fl[kCand + 2])
+        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
+    return SDPC_OK;
+}
+
+double since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// largest alpha in (0, 1] with Y + alpha dY positive definite (parallel candidate tests)
+sdpc_status dual_step(sdpc_handle *h, double *alpha_out) {
+    launch_dual_step(h->d, h->Y, h->dY, kCand, kDualRounds, h->cand, h->flags, h->alphas, h->st);
+    HIPCHK(h, hipGetLastError());
+    double br[3];
+    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 3 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    *alpha_out = br[0];
+    return SDPC_OK;
+}
+
+struct IterInfo {
+    bool stop = false;
+    double pobj, dobj, relgap, pinf, dinf, mu, beta;
+};
+
+sdpc_status read_metrics(sdpc_handle *h, IterInfo &it) {
+    DevStruct &d = h->d;
+    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, nullptr, h->st);
+    HIPCHK(h, hipGetLastError());
+    double sc[8];
+    HIPCHK(h, hipMemcpyAsync(sc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (sc[5] != 0.0) return fail(h, SDPC_E_NUMERIC, "non-finite iterate");
+    it.pobj = sc[0];
+    it.dobj = sc[1];
+    it.relgap = std::fabs(sc[0] - sc[1]) / std::max(1.0, (std::fabs(sc[0]) + std::fabs(sc[1])) / 2.0);
+    it.pinf = sc[2] / (1.0 + h->bmax);
+    it.dinf = sc[3] / (1.0 + h->a0max);
+    it.mu = sc[4] / h->n;
+    const bool feas = it.pinf <= h->prm.feas_tol && it.dinf <= h->prm.feas_tol;
+    it.beta = feas ? h->prm.beta_feas : h->prm.beta_infeas;
+    it.stop = it.relgap <= h->prm.gap_tol && feas;
+    return SDPC_OK;
+}
+
+void fill_result(sdpc_handle *h, const IterInfo &it, sdpc_result *res) {
+    if (!res) return;
+    res->iters = h->iters;
+    res->pobj = it.pobj;
+    res->dobj = it.dobj;
+    res->rel_gap = it.relgap;
+    res->pinf = it.pinf;
+    res->dinf = it.dinf;
+    res->mu = it.mu;
+    res->beta = it.beta;
+    res->alpha_p = h->last_alpha[0];
+    res->alpha_d = h->last_alpha[1];
+    res->device_bytes = h->bytes;
+}
+
+// One iteration.  *done = true when the stopping test held (no update).
+sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
+    DevStruct &d = h->d;
+    hipStream_t st = h->st;
+    IterInfo it;
+    TRY(read_metrics(h, it));
+    *done = it.stop;
+    if (it.stop) {
+        fill_result(h, it, res);
+        return SDPC_OK;
+    }
+    const double bm = it.beta * it.mu;
+    TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false));
+    double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
+    hipEvent_t *ev = h->ev;
+    HIPCHK(h, hipEventRecord(ev[0], st));
+    // right-hand side: g = b - beta mu A(Y^{-1}) + A(X^ G Y^{-1})
+    launch_scm_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
+    launch_rhs(d, h->Yi, h->hcol, bm, h->g, st);
+    HIPCHK(h, hipEventRecord(ev[1], st));
+    HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
+    launch_potrf(d.m, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    launch_potrs(d.m, h->B, h->ldb, h->pwork, h->g, h->ty, h->dz, st);
+    HIPCHK(h, hipEventRecord(ev[2], st));
+    // dY = G - sum dz_k A_k ; dX on E
+    launch_assemble(d, h->dz, 0.0, 1.0, h->G, h->dY, st);
+    launch_dense_times_agg(d, h->Xh, h->dY, h->W, st);
+    launch_dX(d, h->W, h->Yi, h->X, bm, h->dX, st);
+    launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
+    HIPCHK(h, hipEventRecord(ev[3], st));
+    HIPCHK(h, hipGetLastError());
+    double ap = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (read_flag(h, kCand + 2))
+        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite");
+    float ms_rhs = 0, ms_chol = 0, ms_pm = 0;
+    (void)hipEventElapsedTime(&ms_rhs, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&ms_chol, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&ms_pm, ev[2], ev[3]);
+    const auto t0 = std::chrono::steady_clock::now();
+    double ad = 0.0;
+    TRY(dual_step(h, &ad));
+    const double ms_ad = since(t0);
+    h->last_alpha[0] = ap;
+    h->last_alpha[1] = ad;
+    if (!(ap > 0.0) || !(ad > 0.0)) return fail(h, SDPC_E_STAGNATION, "step length collapsed to zero");
+    const double gm = h->prm.gamma;
+    launch_axpy_E(d, h->X, h->dX, nullptr, 0, gm * ap, st);
+    launch_axpy_E(d, h->Y, h->dY, nullptr, 0, gm * ad, st);
+    launch_axpy_vec(d.m, h->z, h->dz, nullptr, 0, gm * ad, st);
+    HIPCHK(h, hipGetLastError());
+    h->iters++;
+    if (res) {
+        res->t_scm_ms += t_scm + ms_rhs;
+        res->t_chol_ms += ms_chol;
+        res->t_pmatrix_ms += ms_pm + ms_ad;
+    }
+    fill_result(h, it, res);
+    if (h->prm.verbose)
+        fprintf(stderr,
+                "it %3d pobj %+.10e dobj %+.10e gap %.2e pinf %.2e dinf %.2e mu %.2e ap %.4f ad %.4f "
+                "scm %.3f chol %.3f pm %.3f ad %.3f ms\n",
+                h->iters, it.pobj, it.dobj, it.relgap, it.pinf, it.dinf, it.mu, ap, ad, t_scm + ms_rhs, ms_chol,
+                ms_pm, ms_ad);
+    return SDPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sdpc_status sdpc_reset(sdpc_handle *h) {
+    if (!h) return SDPC_E_ARG;
+    launch_init_point(h->d, h->prm.lambda0, h->X, h->Y, h->z, h->st);
+    HIPCHK(h, hipGetLastError());
+    h->iters = 0;
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_step(sdpc_handle *h, sdpc_result *res) {
+    if (!h) return SDPC_E_ARG;
+    if (res) std::memset(res, 0, sizeof(*res));
+    const auto t0 = std::chrono::steady_clock::now();
+    bool done = false;
+    sdpc_status s = step_impl(h, res, &done);
+    if (res) {
+        res->status = s;
+        res->t_total_ms = since(t0);
+    }
+    return s;
+}
+
+sdpc_status sdpc_solve(sdpc_handle *h, sdpc_result *res) {
+    if (!h) return SDPC_E_ARG;
+    sdpc_result r;
+    std::memset(&r, 0, sizeof(r));
+    const auto t0 = std::chrono::steady_clock::now();
+    sdpc_status s = sdpc_reset(h);
+    bool done = false;
+    while (s == SDPC_OK) {
+        s = step_impl(h, &r, &done);
+        if (s != SDPC_OK || done) break;
+        if (h->iters >= h->prm.max_iter) {
+            IterInfo it;
+            s = read_metrics(h, it);
+            if (s == SDPC_OK) {
+                fill_result(h, it, &r);
+                s = it.stop ? SDPC_OK : fail(h, SDPC_E_MAXITER, "iteration limit reached");
+            }
+            break;
+        }
+    }
+    r.status = s;
+    r.iters = h->iters;
+    r.t_total_ms = since(t0);
+    r.device_bytes = h->bytes;
+    if (res) *res = r;
+    return s;
+}
+
+sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E, double *d_B, int64_t ldb,
+                     int32_t factor) {
+    if (!h || !d_Xbar_E || !d_Y_E || !d_B || ldb < h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_scm arguments") : SDPC_E_ARG;
+    return scm_phase(h, d_Xbar_E, d_Y_E, d_B, ldb, factor != 0);
+}
+
+sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m) {
+    if (!h || !d_B || m < 0 || ldb < m || m > h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_potrf arguments") : SDPC_E_ARG;
+    HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), h->st));
+    launch_potrf(m, d_B, ldb, h->pwork, h->flags + kCand + 2, h->st);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const int f = read_flag(h, kCand + 2);
+    if (f) return fail(h, SDPC_E_NOT_PD, "matrix not positive definite at pivot " + std::to_string(f - 1));
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_pattern(const sdpc_handle *h, int64_t *nslot, int32_t *iE, int32_t *jE, int32_t *perm,
+                             int32_t *ncliques) {
+    if (!h) return SDPC_E_ARG;
+    if (nslot) *nslot = h->S.nslot;
+    if (iE || jE)
+        for (int64_t s = 0; s < h->S.nslot; ++s) {
+            const int r = h->slot_row_h[s], c = h->slot_col_h[s];
+            if (iE) iE[s] = r >= 0 ? h->S.perm[r] : -1;
+            if (jE) jE[s] = c >= 0 ? h->S.perm[c] : -1;
+        }
+    if (perm) std::copy(h->S.perm.begin(), h->S.perm.end(), perm);
+    if (ncliques) *ncliques = h->S.ncl;
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_cliques(const sdpc_handle *h, int64_t *cptr, int32_t *cidx, int32_t *nS) {
+    if (!h) return SDPC_E_ARG;
+    const Symbolic &S = h->S;
+    int64_t off = 0;
+    if (cptr) cptr[0] = 0;
+    for (int r = 0; r < S.ncl; ++r) {
+        const int f = S.cl_first[r];
+        for (int64_t t = S.sptr[f]; t < S.sptr[f + 1]; ++t) {
+            if (cidx) cidx[off] = S.perm[S.sidx[t]];
+            ++off;
+        }
+        if (cptr) cptr[r + 1] = off;
+        if (nS) nS[r] = S.cl_first[r + 1] - f;
+    }
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_solution(const sdpc_handle *hc, double *d_Xbar_E, double *d_Y_E, double *d_z) {
+    sdpc_handle *h = const_cast<sdpc_handle *>(hc);
+    if (!h) return SDPC_E_ARG;
+    const size_t ns = size_t(h->S.nslot) * sizeof(double);
+    if (d_Xbar_E) HIPCHK(h, hipMemcpyAsync(d_Xbar_E, h->X, ns, hipMemcpyDeviceToDevice, h->st));
+    if (d_Y_E) HIPCHK(h, hipMemcpyAsync(d_Y_E, h->Y, ns, hipMemcpyDeviceToDevice, h->st));
+    if (d_z) HIPCHK(h, hipMemcpyAsync(d_z, h->z, size_t(h->m) * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E, const double *d_z) {
+    if (!h || !d_Xbar_E || !d_Y_E || !d_z) return h ? fail(h, SDPC_E_ARG, "null state pointer") : SDPC_E_ARG;
+    const size_t ns = size_t(h->S.nslot) * sizeof(double);
+    HIPCHK(h, hipMemcpyAsync(h->X, d_Xbar_E, ns, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->Y, d_Y_E, ns, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->z, d_z, size_t(h->m) * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    launch_mask_E(h->d, h->X, h->st);
+    launch_mask_E(h->d, h->Y, h->st);
+    HIPCHK(h, hipGetLastError());
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_factors(const sdpc_handle *hc, double *d_N, double *d_Lhat) {
+    sdpc_handle *h = const_cast<sdpc_handle *>(hc);
+    if (!h) return SDPC_E_ARG;
+    const size_t ns = size_t(h->S.nslot) * sizeof(double);
+    if (d_N) HIPCHK(h, hipMemcpyAsync(d_N, h->N, ns, hipMemcpyDeviceToDevice, h->st));
+    if (d_Lhat) HIPCHK(h, hipMemcpyAsync(d_Lhat, h->Lhat, ns, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_dense(const sdpc_handle *hc, double *d_Xhat, double *d_Yinv) {
+    sdpc_handle *h = const_cast<sdpc_handle *>(hc);
+    if (!h) return SDPC_E_ARG;
+    const size_t nn = size_t(h->n) * h->n * sizeof(double);
+    if (d_Xhat) HIPCHK(h, hipMemcpyAsync(d_Xhat, h->Xh, nn, hipMemcpyDeviceToDevice, h->st));
+    if (d_Yinv) HIPCHK(h, hipMemcpyAsync(d_Yinv, h->Yi, nn, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_direction(const sdpc_handle *hc, double *d_dz, double *d_dX_E, double *d_dY_E, double *alpha) {
+    sdpc_handle *h = const_cast<sdpc_handle *>(hc);
+    if (!h) return SDPC_E_ARG;
+    const size_t ns = size_t(h->S.nslot) * sizeof(double);
+    if (d_dz) HIPCHK(h, hipMemcpyAsync(d_dz, h->dz, size_t(h->m) * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    if (d_dX_E) HIPCHK(h, hipMemcpyAsync(d_dX_E, h->dX, ns, hipMemcpyDeviceToDevice, h->st));
+    if (d_dY_E) HIPCHK(h, hipMemcpyAsync(d_dY_E, h->dY, ns, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (alpha) {
+        alpha[0] = h->last_alpha[0];
+        alpha[1] = h->last_alpha[1];
+    }
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5) {
+    if (!h || !ms5) return SDPC_E_ARG;
+    for (int i = 0; i < 5; ++i) ms5[i] = h->scm_ms[i];
+    return SDPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,316 @@
+// Factorisations on the clique / block structure.
+//
+//  k_sn_chol      Y = N N^T, supernodal right-looking Cholesky on the storage
+//                 blocks (type (v) of Section 3.1).  One workgroup walks the
+//                 blocks in elimination order; each panel is factorised in LDS
+//                 and its update is scattered into the ancestor panels through
+//                 precomputed slots.  blockIdx.x selects a candidate
+//                 Y + alpha_c dY, which turns the same kernel into a parallel
+//                 positive-definiteness test for the dual step length
+//                 (Section 2.2, Step 3).
+//  k_dinv         inverses of the diagonal blocks of a factor (used by the
+//                 multi-right-hand-side substitutions).
+//  k_algorithm1   Algorithm 1: per clique C_r, reverse the order of
+//                 Xbar(C_r, C_r) (Step 2-1), factorise it as M_r M_r^T
+//                 (Step 2-2), form L_r = P_r M_r^{-T} P_r^T (Step 2-3) and
+//                 store its first |S_r| columns as Lhat(C_r, S_r) (Step 3).
+//  k_alpha_cl     eq. primal_length2: per clique the largest alpha in (0, 1]
+//                 keeping Xbar(C_r,C_r) + alpha dX(C_r,C_r) positive definite,
+//                 found by bisection on the Cholesky test.
+#include "kernels.h"
+
+namespace sdpc {
+
+namespace {
+
+constexpr int kCholThreads = 256;
+
+__global__ void __launch_bounds__(kCholThreads)
+k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+          const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
+          const int *__restrict__ up_pair, const int *__restrict__ up_slot, const double *__restrict__ Y,
+          const double *__restrict__ dY, const double *__restrict__ bracket, int round, double *__restrict__ Lbase,
+          int64_t stride, int *__restrict__ fail) {
+    extern __shared__ double P[];
+    const int tid = threadIdx.x;
+    const int cand = blockIdx.x;
+    double *L = Lbase + cand * stride;
+    double a = 0.0;
+    if (dY) {
+        // round 0: a logarithmic grid 1e-8 .. 1; later rounds: an even grid inside
+        // the bracket (lo, hi) left by the previous round (bracket[2] != 0: settled)
+        const int K = gridDim.x;
+        if (round == 0) {
+            a = pow(10.0, -8.0 * double(K - 1 - cand) / double(K - 1));
+        } else {
+            if (bracket[2] != 0.0) {
+                if (tid == 0) fail[cand] = 0;
+                return;
+            }
+            a = bracket[0] + (bracket[1] - bracket[0]) * double(cand + 1) / double(K + 1);
+        }
+    }
+    // padding slots of the inputs are ignored (the factor stores an exact zero there)
+    for (int64_t s = tid; s < nslot; s += blockDim.x)
+        L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? (Y[s] + a * dY[s]) : Y[s]);
+    __threadfence_block();
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+        const int F = bl_first[b];
+        const int w = bl_first[b + 1] - F;
+        const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
+        const int64_t off = bl_off[b];
+        for (int i = tid; i < h * w; i += blockDim.x) P[i] = L[off + i];
+        __syncthreads();
+        for (int j = 0; j < w; ++j) {
+            const double d = P[j + h * j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (tid == 0) fail[cand] = b + 1;
+                return;   // uniform: every thread read the same pivot
+            }
+            const double rd = sqrt(d);
+            const double inv = 1.0 / rd;
+            for (int i = j + 1 + tid; i < h; i += blockDim.x) P[i + h * j] *= inv;
+            __syncthreads();
+            if (tid == 0) P[j + h * j] = rd;
+            const int nk = w - j - 1;
+            for (int idx = tid; idx < nk * h; idx += blockDim.x) {
+                const int k = j + 1 + idx / h;
+                const int i = idx % h;
+                if (i >= k) P[i + h * k] -= P[i + h * j] * P[k + h * j];
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < h * w; i += blockDim.x) L[off + i] = P[i];
+        for (int64_t t = up_ptr[b] + tid; t < up_ptr[b + 1]; t += blockDim.x) {
+            const int s = up_slot[t];
+            if (s < 0) continue;
+            const int pr = up_pair[t];
+            const int ra = w + (pr & 0xffff), rc = w + (pr >> 16);
+            double v = 0.0;
+            for (int j = 0; j < w; ++j) v += P[ra + h * j] * P[rc + h * j];
+            L[s] -= v;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (tid == 0) fail[cand] = 0;
+}
+
+__global__ void __launch_bounds__(64)
+k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
+       const int64_t *__restrict__ bl_dinv, const double *__restrict__ L, double *__restrict__ Dinv,
+       int *__restrict__ fail) {
+    __shared__ double D[64 * 64];
+    const int b = blockIdx.x;
+    const int F = bl_first[b];
+    const int w = bl_first[b + 1] - F;
+    const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
+    const double *P = L + bl_off[b];
+    for (int i = threadIdx.x; i < w * w; i += blockDim.x) {
+        const int r = i % w, c = i / w;
+        D[i] = (r >= c) ? P[r + int64_t(h) * c] : 0.0;
+    }
+    __syncthreads();
+    double *X = Dinv + bl_dinv[b];
+    const int k = threadIdx.x;
+    if (k < w) {
+        // column k of D^{-1} by forward substitution
+        double xs[64];
+        for (int i = 0; i < w; ++i) xs[i] = 0.0;
+        const double dk = D[k + w * k];
+        if (!(dk != 0.0) || !isfinite(dk)) atomicExch(fail, b + 1);
+        xs[k] = 1.0 / dk;
+        for (int i = k + 1; i < w; ++i) {
+            double acc = 0.0;
+            for (int j = k; j < i; ++j) acc += D[i + w * j] * xs[j];
+            xs[i] = -acc / D[i + w * i];
+        }
+        for (int i = 0; i < w; ++i) X[i + w * k] = xs[i];
+    }
+}
+
+// In-LDS Cholesky of the c x c lower triangle of A (column-major, ld c).
+// Returns false (uniformly) on a non-positive pivot.  blockDim = 64.
+__device__ bool lds_chol(double *A, int c) {
+    const int tid = threadIdx.x;
+    for (int j = 0; j < c; ++j) {
+        const double d = A[j + c * j];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        const double rd = sqrt(d);
+        const double inv = 1.0 / rd;
+        for (int i = j + 1 + tid; i < c; i += blockDim.x) A[i + c * j] *= inv;
+        __syncthreads();
+        if (tid == 0) A[j + c * j] = rd;
+        const int nk = c - j - 1;
+        for (int idx = tid; idx < nk * c; idx += blockDim.x) {
+            const int k = j + 1 + idx / c;
+            const int i = idx % c;
+            if (i >= k) A[i + c * k] -= A[i + c * j] * A[k + c * j];
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(64)
+k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
+             const int *__restrict__ cl_map, const int *__restrict__ cl_first, const double *__restrict__ Xbar,
+             double *__restrict__ Lhat, int *__restrict__ fail) {
+    extern __shared__ double sm[];
+    const int r = blockIdx.x;
+    const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
+    const int ns = cl_first[r + 1] - cl_first[r];
+    const int *map = cl_map + cl_map_ptr[r];
+    double *Z = sm;          // c x c: P_r Xbar(C_r,C_r) P_r^T, then M_r
+    double *Mi = sm + c * c; // c x c: M_r^{-1}
+    const int tid = threadIdx.x;
+    // Step 2-1: Z(a, b) = Xbar(C[c-1-a], C[c-1-b]); packed lower index of (i, j), i >= j:
+    // j * (2c - j + 1) / 2 + (i - j)
+    for (int idx = tid; idx < c * c; idx += blockDim.x) {
+        const int a = idx % c, bb = idx / c;
+        if (a < bb) { Z[idx] = 0.0; continue; }
+        const int i = c - 1 - bb, j = c - 1 - a;   // original clique indices, i >= j
+        Z[idx] = Xbar[map[j * (2 * c - j + 1) / 2 + (i - j)]];
+    }
+    __syncthreads();
+    // Step 2-2: Z = M_r M_r^T
+    if (!lds_chol(Z, c)) {
+        if (tid == 0) atomicCAS(fail, 0, r + 1);
+        return;
+    }
+    // M_r^{-1}, column k by forward substitution (threads over k)
+    for (int k = tid; k < c; k += blockDim.x) {
+        for (int i = 0; i < k; ++i) Mi[i + c * k] = 0.0;
+        Mi[k + c * k] = 1.0 / Z[k + c * k];
+        for (int i = k + 1; i < c; ++i) {
+            double acc = 0.0;
+            for (int j = k; j < i; ++j) acc += Z[i + c * j] * Mi[j + c * k];
+            Mi[i + c * k] = -acc / Z[i + c * i];
+        }
+    }
+    __syncthreads();
+    // Steps 2-3 and 3: L_r(i, j) = (P M^{-T} P)(i, j) = M^{-1}(c-1-j, c-1-i), first ns columns
+    for (int j = 0; j < ns; ++j)
+        for (int i = j + tid; i < c; i += blockDim.x)
+            Lhat[map[j * (2 * c - j + 1) / 2 + (i - j)]] = Mi[(c - 1 - j) + c * (c - 1 - i)];
+}
+
+__global__ void __launch_bounds__(64)
+k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
+           const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
+           double *__restrict__ alpha_cl) {
+    extern __shared__ double A[];
+    const int r = blockIdx.x;
+    const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
+    const int *map = cl_map + cl_map_ptr[r];
+    const int tid = threadIdx.x;
+    auto test = [&](double al) -> bool {
+        // reversed row/column order, the pivot order Algorithm 1 factorises in
+        for (int idx = tid; idx < c * c; idx += blockDim.x) {
+            const int a = idx % c, bb = idx / c;
+            if (a < bb) continue;
+            const int i = c - 1 - bb, j = c - 1 - a;
+            const int s = map[j * (2 * c - j + 1) / 2 + (i - j)];
+            A[idx] = Xbar[s] + al * dX[s];
+        }
+        __syncthreads();
+        const bool ok = lds_chol(A, c);
+        __syncthreads();
+        return ok;
+    };
+    double res;
+    if (test(1.0)) {
+        res = 1.0;
+    } else {
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 52; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (test(mid)) lo = mid; else hi = mid;
+        }
+        res = lo;
+    }
+    if (tid == 0) alpha_cl[r] = res;
+}
+
+// After a round of candidate tests (fail[c] == 0: Y + a_c dY positive definite),
+// keep the longest prefix of successes and narrow bracket = (lo, hi, settled).
+__global__ void k_bracket(int K, int round, const int *__restrict__ fail, double *__restrict__ bracket) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (round > 0 && bracket[2] != 0.0) return;
+    int best = -1;
+    for (int c = 0; c < K; ++c) {
+        if (fail[c] != 0) break;
+        best = c;
+    }
+    auto cand = [&](int c) {
+        return round == 0 ? pow(10.0, -8.0 * double(K - 1 - c) / double(K - 1))
+                          : bracket[0] + (bracket[1] - bracket[0]) * double(c + 1) / double(K + 1);
+    };
+    if (round == 0) {
+        if (best == K - 1) { bracket[0] = 1.0; bracket[1] = 1.0; bracket[2] = 1.0; return; }
+        if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 1.0; return; }
+        const double lo = cand(best), hi = cand(best + 1);
+        bracket[0] = lo; bracket[1] = hi; bracket[2] = 0.0;
+        return;
+    }
+    const double lo = best >= 0 ? cand(best) : bracket[0];
+    const double hi = best + 1 < K ? cand(best + 1) : bracket[1];
+    bracket[0] = lo;
+    bracket[1] = hi;
+}
+
+__global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__restrict__ v, double *out) {
+    __shared__ double sh[1024];
+    double m = 1.0;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) m = fmin(m, v[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+}  // namespace
+
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st) {
+    const size_t lds = size_t(d.max_panel) * sizeof(double);
+    hipLaunchKernelGGL(k_sn_chol, dim3(1), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
+                       d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, (const double *)nullptr,
+                       (const double *)nullptr, 0, L, int64_t(0), fail);
+}
+
+void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int ncand, int rounds, double *cand,
+                      int *fail, double *bracket, hipStream_t st) {
+    const size_t lds = size_t(d.max_panel) * sizeof(double);
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_sn_chol, dim3(ncand), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
+                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket, r,
+                           cand, d.nslot, fail);
+        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, ncand, r, (const int *)fail, bracket);
+    }
+}
+
+void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st) {
+    hipLaunchKernelGGL(k_dinv, dim3(d.nb), dim3(64), 0, st, d.bl_first, d.bl_rptr, d.bl_off, d.bl_dinv, L,
+                       Dinv, fail);
+}
+
+void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail, hipStream_t st) {
+    const size_t lds = size_t(2) * d.max_clique * d.max_clique * sizeof(double);
+    hipLaunchKernelGGL(k_algorithm1, dim3(d.ncl), dim3(64), lds, st, d.cl_ptr, d.cl_map_ptr, d.cl_map,
+                       d.cl_first, Xbar, Lhat, fail);
+}
+
+void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX, double *alpha_cl,
+                          double *out, hipStream_t st) {
+    const size_t lds = size_t(d.max_clique) * d.max_clique * sizeof(double);
+    hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(64), lds, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
+                       alpha_cl);
+    hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, alpha_cl, out);
+}
+
+}  // namespace sdpc

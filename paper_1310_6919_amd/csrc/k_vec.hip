@@ -1,0 +1,173 @@
+// Assembly of matrices on the storage layout, state metrics, vector updates.
+//
+//   Y = A_0 - sum_k z_k A_k                      (dual slack, Section 1 (D))
+//   G = A_0 - sum_k z_k A_k - Y                   (dual residual)
+//   dY = G - sum_k dz_k A_k                       (Section 2.2, HKM direction)
+// are all one gather per storage slot over the A_k entries that land there
+// (fixed order, no atomics).
+#include "kernels.h"
+
+namespace sdpc {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_assemble(int64_t nslot, const int64_t *__restrict__ ptr, const int *__restrict__ kk,
+                           const double *__restrict__ val, const double *__restrict__ y, double a0,
+                           double c1, const double *__restrict__ in1, double *__restrict__ out) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        double acc = 0.0;
+        for (int64_t t = ptr[s]; t < ptr[s + 1]; ++t) {
+            const int k = kk[t];
+            const double coef = (k == 0) ? a0 : -y[k - 1];
+            acc += coef * val[t];
+        }
+        if (in1) acc += c1 * in1[s];
+        out[s] = acc;
+    }
+}
+
+// Block-wide reductions (sum and max), blockDim = 1024.
+__device__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (t < o) sh[t] = fmax(sh[t], sh[t + o]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// scal[0] = A_0 . X, scal[1] = b . z, scal[2] = max_k |b_k - A_k . X|,
+// scal[3] = max |G|, scal[4] = X . Y (on E), scal[5] = 1 if anything non-finite
+__global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const int64_t *__restrict__ con_ptr,
+                                                  const int *__restrict__ con_slot,
+                                                  const double *__restrict__ con_val,
+                                                  const double *__restrict__ b, const double *__restrict__ wE,
+                                                  const double *__restrict__ X, const double *__restrict__ Y,
+                                                  const double *__restrict__ z, const double *__restrict__ G,
+                                                  double *__restrict__ scal) {
+    __shared__ double sh[1024];
+    const int t = threadIdx.x;
+    double pobj = 0.0, bz = 0.0, rmax = 0.0, gmax = 0.0, xy = 0.0;
+    bool bad = false;
+    for (int k = t; k <= m; k += blockDim.x) {
+        double a = 0.0;
+        for (int64_t e = con_ptr[k]; e < con_ptr[k + 1]; ++e) a += con_val[e] * X[con_slot[e]];
+        if (k == 0) {
+            pobj = a;
+        } else {
+            const double r = b[k - 1] - a;
+            rmax = fmax(rmax, fabs(r));
+            bz += b[k - 1] * z[k - 1];
+            bad |= !isfinite(z[k - 1]);
+        }
+    }
+    for (int64_t s = t; s < nslot; s += blockDim.x) {
+        const double w = wE[s];
+        xy += w * X[s] * Y[s];
+        gmax = fmax(gmax, fabs(G[s]));
+        bad |= !(isfinite(X[s]) && isfinite(Y[s]));
+    }
+    pobj = block_sum(pobj, sh);
+    bz = block_sum(bz, sh);
+    rmax = block_max(rmax, sh);
+    gmax = block_max(gmax, sh);
+    xy = block_sum(xy, sh);
+    const double nb = block_max(bad ? 1.0 : 0.0, sh);
+    if (t == 0) {
+        scal[0] = pobj;
+        scal[1] = bz;
+        scal[2] = rmax;
+        scal[3] = gmax;
+        scal[4] = xy;
+        scal[5] = nb;
+    }
+}
+
+__global__ void k_axpy(int64_t len, double *__restrict__ x, const double *__restrict__ dx, double coef) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < len;
+         s += int64_t(gridDim.x) * blockDim.x)
+        x[s] += coef * dx[s];
+}
+
+__global__ void k_init(int64_t nslot, const double *__restrict__ wE, double lambda, double *X, double *Y,
+                       int m, double *z) {
+    // diagonal slots are exactly those with weight 1
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        const double v = (wE[s] == 1.0) ? lambda : 0.0;
+        X[s] = v;
+        Y[s] = v;
+    }
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < m; k += int64_t(gridDim.x) * blockDim.x)
+        z[k] = 0.0;
+}
+
+__global__ void k_mask(int64_t nslot, const double *__restrict__ wE, double *v) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot;
+         s += int64_t(gridDim.x) * blockDim.x)
+        if (wE[s] == 0.0) v[s] = 0.0;
+}
+
+int grid_for(int64_t len) {
+    int64_t g = (len + kThreads - 1) / kThreads;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return int(g);
+}
+
+}  // namespace
+
+void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, const double *in1,
+                     double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, d.asm_ptr,
+                       d.asm_k, d.asm_val, y, a0, c1, in1, out);
+}
+
+void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z, double *G,
+                    double *scal, double * /*work*/, hipStream_t st) {
+    // G = A_0 - sum z_k A_k - Y
+    launch_assemble(d, z, 1.0, -1.0, Y, G, st);
+    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(1024), 0, st, d.m, d.nslot, d.con_ptr, d.con_slot,
+                       d.con_val, d.b, d.wE, X, Y, z, G, scal);
+}
+
+void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double * /*alpha*/, int /*which*/,
+                   double coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, x, dx, coef);
+}
+
+void launch_axpy_vec(int m, double *x, const double *dx, const double * /*alpha*/, int /*which*/,
+                     double coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(m)), dim3(kThreads), 0, st, int64_t(m), x, dx, coef);
+}
+
+void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z, hipStream_t st) {
+    hipLaunchKernelGGL(k_init, dim3(grid_for(d.nslot > d.m ? d.nslot : d.m)), dim3(kThreads), 0, st,
+                       d.nslot, d.wE, lambda, X, Y, d.m, z);
+}
+
+void launch_mask_E(const DevStruct &d, double *v, hipStream_t st) {
+    hipLaunchKernelGGL(k_mask, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, d.wE, v);
+}
+
+}  // namespace sdpc

@@ -1,0 +1,138 @@
+// Device data structures and kernel launchers (host-callable).
+//
+// Storage layout shared by Lhat, N and every E-vector (Section 3.1: "the
+// structure of the memory allocated to Lhat is identical to that of N"):
+// block b owns columns [bl_first[b], bl_first[b+1]) and rows
+// bl_rows[bl_rptr[b] .. bl_rptr[b+1]) (own columns first); its panel is the
+// h x w column-major array at offset bl_off[b].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sdpc {
+
+struct DevStruct {
+    int n = 0, m = 0, nb = 0, ncl = 0;
+    int64_t nslot = 0;
+    int max_h = 0, max_w = 0, max_clique = 0;
+    int64_t max_panel = 0;              // max over blocks of h * w
+    // blocks
+    const int *bl_first = nullptr;      // nb + 1
+    const int64_t *bl_rptr = nullptr;   // nb + 1
+    const int *bl_rows = nullptr;       // sum h
+    const int64_t *bl_off = nullptr;    // nb + 1
+    const int *bl_subfirst = nullptr;   // nb
+    const int *bl_fslot = nullptr;      // sum h: forward solve slot of each row (-1: none)
+    const int *bl_bslot = nullptr;      // sum h: backward solve slot of each row (-1: none)
+    const int64_t *bl_dinv = nullptr;   // nb + 1: offsets of the w x w diagonal-block inverses
+    const int64_t *up_ptr = nullptr;    // nb + 1: update pairs of each block
+    const int *up_pair = nullptr;       // (a | c << 16), a >= c, indices into the non-own rows
+    const int *up_slot = nullptr;       // target slot, -1 if not stored (value is exactly zero)
+    int nfwd = 0, nbwd = 0;
+    const int *col_block = nullptr;     // n: block of every column
+    const int *slot_row = nullptr;      // nslot: row position of an E slot, -1 on padding
+    const int *slot_col = nullptr;      // nslot: column position of an E slot, -1 on padding
+    // cliques (fundamental supernodes)
+    const int *cl_first = nullptr;      // ncl + 1
+    const int64_t *cl_ptr = nullptr;    // ncl + 1: offsets into cl_rows
+    const int *cl_rows = nullptr;       // C_r in positions, ascending
+    const int64_t *cl_map_ptr = nullptr;// ncl + 1
+    const int *cl_map = nullptr;        // packed lower-triangle slots of C_r x C_r, column by column
+    // E-vector weights: 1 (diagonal), 2 (off-diagonal), 0 (padding); also the E mask
+    const double *wE = nullptr;
+    // assembly: slot s collects sum_t asm_val[t] * coef(asm_k[t]) for t in asm_ptr[s]..
+    const int64_t *asm_ptr = nullptr;   // nslot + 1
+    const int *asm_k = nullptr;
+    const double *asm_val = nullptr;
+    // constraints k = 0..m: lower entries (pi >= pj positions), slot, value * multiplicity
+    const int64_t *con_ptr = nullptr;   // m + 2
+    const int *con_pi = nullptr, *con_pj = nullptr, *con_slot = nullptr;
+    const double *con_val = nullptr;
+    const double *b = nullptr;          // m
+    // Schur complement: single diagonal entry per A_k (max-cut form)
+    int hadamard = 0;
+    const int *had_pos = nullptr;       // m
+    const double *had_val = nullptr;    // m
+    // general path: A_q restricted to its nonzero columns K_q, full symmetric CSC
+    const int64_t *kq_ptr = nullptr;    // m + 1: columns of A_q are kq_col[kq_ptr[q]..]
+    const int *kq_col = nullptr;
+    const int64_t *aq_cptr = nullptr;   // (sum |K_q|) + 1, indexed by the global column id
+    const int *aq_row = nullptr;
+    const double *aq_val = nullptr;
+    // union support S of A_1..A_m (full symmetric), grouped by row
+    int64_t nS = 0;
+    const int64_t *S_rowptr = nullptr;  // n + 1
+    const int *S_col = nullptr;         // column of each support entry
+    const int64_t *am_ptr = nullptr;    // m + 1: entries of A_p as (support index, value)
+    const int64_t *am_sidx = nullptr;
+    const double *am_val = nullptr;
+    // aggregate pattern, full symmetric CSC by columns with E slots (for G and dY)
+    const int64_t *ag_cptr = nullptr;   // n + 1
+    const int *ag_row = nullptr;
+    const int *ag_slot = nullptr;
+};
+
+// ---- assembly and vectors (k_vec.hip)
+// out[s] = sum_t asm_val[t] * coef_k  + c1 * in1[s]; coef_0 = a0, coef_k = -y[k-1]
+void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, const double *in1,
+                     double *out, hipStream_t st);
+// scal[...] <- pobj, dobj, max|r|, max|G|, X.Y, also G_E (see k_vec.hip)
+void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z,
+                    double *G, double *scal, double *work, hipStream_t st);
+void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha_scale,
+                   int which, double gamma, hipStream_t st);
+void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha_scale, int which,
+                     double gamma, hipStream_t st);
+void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z,
+                       hipStream_t st);
+void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
+
+// ---- factorisations (k_factor.hip)
+// Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st);
+// largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of ncand
+// parallel factorisations (log grid, then even grids inside the bracket); the result is
+// bracket[0] (a lower bound; bracket[1] an upper bound), all on the device
+void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int ncand, int rounds,
+                      double *cand, int *fail, double *bracket, hipStream_t st);
+void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
+// Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
+void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,
+                       hipStream_t st);
+// eq. primal_length2: per-clique maximal step, then the minimum into *out
+void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX,
+                          double *alpha_cl, double *out, hipStream_t st);
+
+// ---- sparse substitutions (k_solve.hip): out = (L L^T)^{-1}, n x n, full symmetric
+int solve_tile_width(const DevStruct &d);
+void launch_inverse_by_solves(const DevStruct &d, const double *L, const double *Dinv, double *out,
+                              hipStream_t st);
+
+// ---- Schur complement (k_scm.hip)
+void launch_scm_hadamard(const DevStruct &d, const double *Xh, const double *Yi, double *B,
+                         int64_t ldb, hipStream_t st);
+// general SCM, one column q at a time (kq_ptr_host: host mirror of kq_ptr); lower triangle
+void launch_scm_general(const DevStruct &d, const int64_t *kq_ptr_host, const double *Xh,
+                        const double *Yi, double *W, double *T, double *B, int64_t ldb,
+                        hipStream_t st);
+// col[p] = A_p . (X^ M Y^{-1}) for M on the aggregate pattern given as an E-vector
+void launch_scm_extra_column(const DevStruct &d, const double *Mvec, const double *Xh,
+                             const double *Yi, double *W, double *T, double *col, hipStream_t st);
+// g_p = b_p - beta mu A_p . Y^{-1} + h_p
+void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g,
+                hipStream_t st);
+// dX on E:  beta mu Y^{-1} - Xbar - sym(X^ dY Y^{-1}) with W = X^ dY (row-major)
+void launch_dX(const DevStruct &d, const double *W, const double *Yi, const double *Xbar,
+               double beta_mu, double *dX, hipStream_t st);
+// W = X^ M (row-major n x n) for M on the aggregate pattern (E-vector)
+void launch_dense_times_agg(const DevStruct &d, const double *Xh, const double *Mvec, double *W,
+                            hipStream_t st);
+
+// ---- dense FP64 Cholesky and SCE solve (k_dense.hip)
+void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
+void launch_potrs(int m, const double *R, int64_t ldb, const double *dinv, const double *g,
+                  double *y, double *x, hipStream_t st);
+size_t potrf_work_doubles(int m);
+
+}  // namespace sdpc

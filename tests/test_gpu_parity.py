@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (FP64 throughout; derived from the arithmetic, the paper fixes
+none): one SCM evaluation involves two sparse triangular inversions and a
+dense product, each backward stable, so entries of B agree to a few hundred
+ulps times the conditioning of the factors; the states used here keep
+cond(X), cond(Y) <= ~50, hence 1e-10 relative to max|B|.  Full solves are
+compared on the objective (1e-7 relative at gap 1e-7) and on z (1e-6 at a
+tighter gap), the targets of the method's comparison with the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sdpgen
+from oracle.symbolic import aggregate_pattern, chordal_structure
+from tests.gpu_common import dev, from_E, golden, host, rel_err, to_E
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_6919_amd import load
+    load()
+
+
+def _create(prob, **kw):
+    from paper_1310_6919_amd import sdpc_create
+    return sdpc_create(prob, **kw)
+
+
+CASES = {
+    "cfg1": lambda: sdpgen.maxcut_cycle_chords(64, 0),
+    "band300": lambda: sdpgen.maxcut_band(300, 20, 0.5, 1),
+    "band_ragged": lambda: sdpgen.maxcut_band(333, 7, 0.7, 2),
+    "normmin": lambda: sdpgen.normmin(100, 10, 8, 0),
+    "random_sdp": lambda: sdpgen.random_sparse_sdp(45, 20, seed=4),
+}
+
+
+# ----------------------------------------------------------------- dense Cholesky
+@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 200, 257])
+def test_potrf_matches_lapack(m):
+    rng = np.random.default_rng(m)
+    prob = sdpgen.maxcut_band(300, 3, 1.0, 0)
+    h = _create(prob)
+    A = sdpgen.random_pd_dense(m, rng, cond=1e3)
+    Bt = dev(A.T.copy()).T            # column-major view
+    upper_marker = np.triu(np.full((m, m), 7.0), 1)
+    Bt += dev(upper_marker.T.copy()).T
+    h.sdpc_potrf(Bt, m)
+    R = np.tril(host(Bt))
+    Rref = np.linalg.cholesky(A)
+    assert rel_err(R, Rref) <= 1e-12 * 1e3
+    assert np.array_equal(np.triu(host(Bt), 1), np.triu(A, 1) + upper_marker)   # strict upper untouched
+    h.close()
+
+
+def test_potrf_reports_not_pd():
+    prob = sdpgen.maxcut_band(100, 3, 1.0, 0)
+    h = _create(prob)
+    A = np.eye(80)
+    A[50, 50] = -1.0
+    Bt = dev(A.T.copy()).T
+    from paper_1310_6919_amd import SdpcError
+    with pytest.raises(SdpcError) as e:
+        h.sdpc_potrf(Bt, 80)
+    assert "pivot 50" in str(e.value)
+    h.close()
+
+
+# ----------------------------------------------------------------- one SCM evaluation
+def _state(prob, rng):
+    rows, cols = aggregate_pattern(prob)
+    Xfull = sdpgen.random_pd_dense(prob.n, rng, cond=8.0)
+    Y = sdpgen.random_pd_on_pattern(prob.n, rows, cols, rng)
+    return Xfull, Y
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_scm_parity(name):
+    prob = CASES[name]()
+    rng = np.random.default_rng(7)
+    Xfull, Y = _state(prob, rng)
+    h = _create(prob)
+    B = h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)))
+    Bg = np.tril(host(B))          # column-major storage -> numpy
+    # oracle: its own chordal extension for the natural order (same E as any postorder of it)
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    E = ch.E_mask()
+    Xh = oracle.maxdet_complete(ch, np.where(E, Xfull, 0.0))
+    A = oracle.scm.problem_mats(prob)
+    Bref = oracle.dense_scm(A, Xh, np.linalg.inv(Y))
+    assert rel_err(Bg, np.tril(Bref)) <= 1e-10
+    # the dense intermediates, in the library's elimination order
+    _, _, perm = h.sdpc_get_pattern()
+    Xd, Yd = h.sdpc_get_dense()
+    assert rel_err(host(Xd), Xh[np.ix_(perm, perm)]) <= 1e-10
+    assert rel_err(host(Yd), np.linalg.inv(Y)[np.ix_(perm, perm)]) <= 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "band_ragged", "normmin"])
+def test_factors_match_textbook(name):
+    prob = CASES[name]()
+    rng = np.random.default_rng(11)
+    Xfull, Y = _state(prob, rng)
+    h = _create(prob)
+    h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)))
+    N, L = h.sdpc_get_factors()
+    iE, jE, perm = h.sdpc_get_pattern()
+    pos = np.empty(prob.n, dtype=int)
+    pos[perm] = np.arange(prob.n)
+    ok = iE >= 0
+    # Y = N N^T and X^{-1} = Lhat Lhat^T in the library's order (unique Cholesky factors)
+    Nref = np.linalg.cholesky(Y[np.ix_(perm, perm)])
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    Xh = oracle.maxdet_complete(ch, np.where(ch.E_mask(), Xfull, 0.0))
+    Lref = oracle.lhat_textbook(Xh[np.ix_(perm, perm)])
+    pi, pj = pos[iE[ok]], pos[jE[ok]]
+    lo_i, lo_j = np.maximum(pi, pj), np.minimum(pi, pj)
+    assert rel_err(host(N)[ok], Nref[lo_i, lo_j]) <= 1e-11
+    assert rel_err(host(L)[ok], Lref[lo_i, lo_j]) <= 1e-10
+    # padding slots hold exact zeros; factors vanish off E (Algorithm 1 keeps Lhat within E)
+    assert np.all(host(N)[~ok] == 0) and np.all(host(L)[~ok] == 0)
+    Lfull = np.zeros((prob.n, prob.n))
+    Lfull[lo_i, lo_j] = host(L)[ok]
+    assert rel_err(Lfull, np.tril(Lref)) <= 1e-10
+    h.close()
+
+
+def test_scm_central_point_pin():
+    # X = mu Y^{-1} on E: X^ = mu Y^{-1}, Lhat = N / sqrt(mu) and B = mu (Y^{-1} o Y^{-1})
+    prob = sdpgen.maxcut_band(200, 6, 0.8, 3)
+    rng = np.random.default_rng(3)
+    rows, cols = aggregate_pattern(prob)
+    Y = sdpgen.random_pd_on_pattern(prob.n, rows, cols, rng)
+    mu = 0.3
+    Yi = np.linalg.inv(Y)
+    h = _create(prob)
+    B = h.sdpc_scm(dev(to_E(h, mu * Yi)), dev(to_E(h, Y)))
+    assert rel_err(np.tril(host(B)), np.tril(mu * Yi * Yi)) <= 1e-10
+    N, L = h.sdpc_get_factors()
+    assert rel_err(host(L), host(N) / np.sqrt(mu)) <= 1e-10
+    h.close()
+
+
+def test_scm_iteration0_gram():
+    # X = Y = lambda I: B = [A_p . A_q]
+    prob = sdpgen.normmin(60, 6, 5, 1)
+    h = _create(prob)
+    lam = 100.0
+    I = np.eye(prob.n)
+    B = np.tril(host(h.sdpc_scm(dev(to_E(h, lam * I)), dev(to_E(h, lam * I)))))
+    Ad = [prob.dense(k) for k in range(1, prob.m + 1)]
+    G = np.array([[np.sum(a * b) for b in Ad] for a in Ad])
+    assert rel_err(B, np.tril(G)) <= 1e-12
+    h.close()
+
+
+def test_scm_factor_flag():
+    prob = CASES["band300"]()
+    rng = np.random.default_rng(5)
+    Xfull, Y = _state(prob, rng)
+    h = _create(prob)
+    B0 = h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)))
+    Bl = np.tril(host(B0))
+    R = h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)), factor=True)
+    Rl = np.tril(host(R))
+    Bs = Bl + np.tril(Bl, -1).T
+    assert rel_err(Rl, np.linalg.cholesky(Bs)) <= 1e-10
+    h.close()
+
+
+def test_scm_rejects_non_pd():
+    prob = CASES["cfg1"]()
+    h = _create(prob)
+    from paper_1310_6919_amd import SdpcError
+    I = np.eye(prob.n)
+    bad = I.copy()
+    bad[3, 3] = -1.0
+    with pytest.raises(SdpcError):
+        h.sdpc_scm(dev(to_E(h, I)), dev(to_E(h, bad)))
+    with pytest.raises(SdpcError):
+        h.sdpc_scm(dev(to_E(h, bad)), dev(to_E(h, I)))
+    h.close()
+
+
+# ----------------------------------------------------------------- one PDIPM iteration
+@pytest.mark.parametrize("name", ["cfg1", "band_ragged", "normmin", "random_sdp"])
+def test_iteration_matches_oracle(name):
+    prob = CASES[name]()
+    rng = np.random.default_rng(21)
+    Xfull, Y = _state(prob, rng)
+    z = rng.standard_normal(prob.m) * 0.1
+    h = _create(prob)
+    h.sdpc_set_state(dev(to_E(h, Xfull)), dev(to_E(h, Y)), dev(z))
+    h.sdpc_step()
+    dz, dX, dY, (ap, ad) = h.sdpc_get_direction()
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    A = oracle.pdipm.permuted_mats(prob, ch)
+    E = ch.E_mask()
+    ref = oracle.mc_direction(ch, A, prob.b, np.where(E, Xfull, 0.0), Y, z)
+    assert rel_err(host(dz), ref["dz"]) <= 1e-9
+    assert rel_err(from_E(h, host(dY)), ref["dY"]) <= 1e-9
+    assert rel_err(from_E(h, host(dX)), ref["dX"]) <= 1e-9
+    assert abs(ap - ref["alpha_p"]) <= 1e-9 * max(1.0, ref["alpha_p"])
+    # the dual step is bracketed by parallel positive-definiteness tests: relative 1e-4
+    assert ad <= ref["alpha_d"] * (1 + 1e-12)
+    assert ad >= ref["alpha_d"] * (1 - 1e-4)
+    h.close()
+
+
+# ----------------------------------------------------------------- full solves
+@pytest.mark.parametrize("seed", range(5))
+def test_solve_cfg1_matches_golden(seed):
+    """Objective against the dense oracle's solution at gap 1e-10 (stored by
+    tests/golden/make_golden.py)."""
+    prob = sdpgen.maxcut_cycle_chords(64, seed)
+    g = golden(f"cfg1_s{seed}")
+    ref_obj = (g["pobj"] + g["dobj"]) / 2
+    h = _create(prob)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    obj = (r["pobj"] + r["dobj"]) / 2
+    assert abs(obj - ref_obj) <= 1e-7 * max(1.0, abs(ref_obj))
+    assert r["rel_gap"] <= 1e-7 and r["pinf"] <= 1e-7 and r["dinf"] <= 1e-7
+    h.close()
+
+
+@pytest.mark.parametrize("name,tol", [("cfg1", 1e-7), ("cfg1", 1e-9), ("normmin", 1e-8), ("random_sdp", 1e-8)])
+def test_solve_matches_mc_oracle(name, tol):
+    """The whole trajectory against the matrix-completion oracle (same method,
+    same E, same step rules): iteration count, objective, and z to 1e-6."""
+    prob = CASES[name]()
+    P = oracle.Params(gap_tol=tol, feas_tol=tol)
+    ref = oracle.mc_pdipm(prob, P)
+    assert ref["status"] == "optimal"
+    h = _create(prob, gap_tol=tol, feas_tol=tol)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    assert r["iters"] == ref["iters"]
+    obj, robj = (r["pobj"] + r["dobj"]) / 2, (ref["pobj"] + ref["dobj"]) / 2
+    assert abs(obj - robj) <= 1e-7 * max(1.0, abs(robj))
+    _, _, z = h.sdpc_get_solution()
+    assert np.abs(host(z) - ref["z"]).max() <= 1e-6 * max(1.0, np.abs(ref["z"]).max())
+    h.close()
+
+
+def test_solve_cycles_closed_form():
+    for n in (5, 8, 13):
+        e = sdpgen.cycle_graph(n)
+        prob = sdpgen.maxcut(n, e, np.ones(len(e)))
+        h = _create(prob, gap_tol=1e-9, feas_tol=1e-9)
+        r = h.sdpc_solve()
+        val = oracle.cycle_sdp_value(n)
+        assert abs(-(r["pobj"] + r["dobj"]) / 2 - val) <= 1e-7 * val
+        h.close()
+
+
+def test_solve_normmin_sigma_max():
+    prob = sdpgen.normmin(150, 10, 12, 2)
+    h = _create(prob, gap_tol=1e-9, feas_tol=1e-9)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    _, _, z = h.sdpc_get_solution()
+    z = host(z)
+    F = prob.meta["F"]
+    Fy = F[0] + np.einsum("i,ijk->jk", z[1:], F[1:])
+    smax = np.linalg.svd(Fy, compute_uv=False)[0]
+    assert abs(z[0] - smax) <= 1e-7 * smax
+    h.close()
