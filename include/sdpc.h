@@ -103,6 +103,9 @@ typedef struct {
     double t_chol_ms;          /* device time: SCM Cholesky and SCE solve (sum)            */
     double t_pmatrix_ms;       /* device time: dX on E and the step lengths (sum)          */
     double t_total_ms;         /* wall time of the call                                    */
+    double t_potrf_ms;         /* device time of the SCM Cholesky alone (sum)              */
+    int32_t n_potrf;           /* SCM Cholesky factorisations timed in t_potrf_ms          */
+    int32_t pad_;
     size_t device_bytes;       /* device workspace held by the handle                      */
 } sdpc_result;
 

@@ -31,8 +31,8 @@ using namespace sdpc;
 
 namespace {
 
-constexpr int kCand = 64;        // dual step-length candidates per round
-constexpr int kDualRounds = 6;   // log grid, then five even refinements: ~3e-10 relative
+constexpr int kCand = 256;       // dual step-length candidates per round (one workgroup each)
+constexpr int kDualRounds = 4;   // log grid, then three even refinements: ~4e-9 relative
 
 struct Timer {
     hipEvent_t a{}, b{};
@@ -60,7 +60,7 @@ struct sdpc_handle {
     double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr, *pwork = nullptr, *ty = nullptr;
-    double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr;
+    double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
     int *flags = nullptr;   // [0..kCand) sn_chol, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2] potrf
     int64_t ldb = 0;
     double last_alpha[2] = {0, 0};
@@ -488,7 +488,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.ag_slot, ag_slot));
     // ---- workspace
     const size_t ns = size_t(S.nslot), nn = size_t(n) * n;
-    h->ldb = std::max<int64_t>(m, 1);
+    h->ldb = int64_t(m) + 1;   // row m carries the SCE right-hand side through the factorisation
     TRY(dalloc(h, &h->X, ns));
     TRY(dalloc(h, &h->Y, ns));
     TRY(dalloc(h, &h->G, ns));
@@ -507,12 +507,13 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->Yi, nn));
     TRY(dalloc(h, &h->W, nn));
     TRY(dalloc(h, &h->T, std::max<size_t>(size_t(d.nS), 1)));
-    TRY(dalloc(h, &h->B, size_t(h->ldb) * m));
+    TRY(dalloc(h, &h->B, size_t(h->ldb) * std::max(m, 1)));
     TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->scal, 16));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
+    TRY(dalloc(h, &h->part, std::max(size_t(2) * dX_chunks(d) * ns, size_t(rhs_had_parts(d)) * n)));
     TRY(dalloc(h, &h->flags, kCand + 8));
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
@@ -720,17 +721,22 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     hipEvent_t *ev = h->ev;
     HIPCHK(h, hipEventRecord(ev[0], st));
     // right-hand side: g = b - beta mu A(Y^{-1}) + A(X^ G Y^{-1})
-    launch_scm_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
+    if (d.hadamard)
+        launch_rhs_hadamard(d, h->G, h->Xh, h->Yi, h->part, h->hcol, st);
+    else
+        launch_scm_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
     launch_rhs(d, h->Yi, h->hcol, bm, h->g, st);
     HIPCHK(h, hipEventRecord(ev[1], st));
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
-    launch_potrf(d.m, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
-    launch_potrs(d.m, h->B, h->ldb, h->pwork, h->g, h->ty, h->dz, st);
+    launch_set_row(d.m, h->g, h->B + d.m, h->ldb, st);
+    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    HIPCHK(h, hipEventRecord(ev[6], st));
+    launch_potrs_bwd(d.m, h->B, h->ldb, h->pwork, h->B + d.m, h->ldb, h->ty, h->dz, st);
     HIPCHK(h, hipEventRecord(ev[2], st));
     // dY = G - sum dz_k A_k ; dX on E
     launch_assemble(d, h->dz, 0.0, 1.0, h->G, h->dY, st);
-    launch_dense_times_agg(d, h->Xh, h->dY, h->W, st);
-    launch_dX(d, h->W, h->Yi, h->X, bm, h->dX, st);
+    launch_zcol(d, h->Xh, h->dY, h->W, st);
+    launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
     launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
     HIPCHK(h, hipEventRecord(ev[3], st));
     HIPCHK(h, hipGetLastError());
@@ -739,7 +745,8 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipStreamSynchronize(st));
     if (read_flag(h, kCand + 2))
         return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite");
-    float ms_rhs = 0, ms_chol = 0, ms_pm = 0;
+    float ms_rhs = 0, ms_chol = 0, ms_pm = 0, ms_potrf = 0;
+    (void)hipEventElapsedTime(&ms_potrf, ev[1], ev[6]);
     (void)hipEventElapsedTime(&ms_rhs, ev[0], ev[1]);
     (void)hipEventElapsedTime(&ms_chol, ev[1], ev[2]);
     (void)hipEventElapsedTime(&ms_pm, ev[2], ev[3]);
@@ -760,6 +767,8 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
         res->t_scm_ms += t_scm + ms_rhs;
         res->t_chol_ms += ms_chol;
         res->t_pmatrix_ms += ms_pm + ms_ad;
+        res->t_potrf_ms += ms_potrf;
+        res->n_potrf += 1;
     }
     fill_result(h, it, res);
     if (h->prm.verbose)

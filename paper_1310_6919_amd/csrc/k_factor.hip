@@ -17,6 +17,7 @@
 //  k_alpha_cl     eq. primal_length2: per clique the largest alpha in (0, 1]
 //                 keeping Xbar(C_r,C_r) + alpha dX(C_r,C_r) positive definite,
 //                 found by bisection on the Cholesky test.
+#include "chol_reg.h"
 #include "kernels.h"
 
 namespace sdpc {
@@ -32,6 +33,9 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
           const double *__restrict__ dY, const double *__restrict__ bracket, int round, double *__restrict__ Lbase,
           int64_t stride, int *__restrict__ fail) {
     extern __shared__ double P[];
+    __shared__ double col[64];   // scaled pivot column of a panel with at most 64 rows
+    __shared__ double colw[32];  // scaled pivot column (block width <= 32), tall panels
+    __shared__ double piv[2];
     const int tid = threadIdx.x;
     const int cand = blockIdx.x;
     double *L = Lbase + cand * stride;
@@ -60,26 +64,101 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
         const int w = bl_first[b + 1] - F;
         const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
         const int64_t off = bl_off[b];
-        for (int i = tid; i < h * w; i += blockDim.x) P[i] = L[off + i];
+        stage_lds<16>(P, L + off, h * w);
         __syncthreads();
-        for (int j = 0; j < w; ++j) {
-            const double d = P[j + h * j];
-            if (!(d > 0.0) || !isfinite(d)) {
-                if (tid == 0) fail[cand] = b + 1;
-                return;   // uniform: every thread read the same pivot
+        // right-looking factorisation of the panel
+        if (h <= 64) {
+            // thread (row rl, quarter q) keeps P(rl, q + 4t) in registers; only the
+            // scaled pivot column (col) and the next pivot (piv) go through LDS
+            const int rl = tid & 63, q = tid >> 6;
+            double a[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = q + 4 * t;
+                a[t] = (rl < h && k < w && (rl >= w || k <= rl)) ? P[rl + h * k] : 0.0;
             }
-            const double rd = sqrt(d);
-            const double inv = 1.0 / rd;
-            for (int i = j + 1 + tid; i < h; i += blockDim.x) P[i + h * j] *= inv;
+            if (tid == 0) piv[0] = P[0];
             __syncthreads();
-            if (tid == 0) P[j + h * j] = rd;
-            const int nk = w - j - 1;
-            for (int idx = tid; idx < nk * h; idx += blockDim.x) {
-                const int k = j + 1 + idx / h;
-                const int i = idx % h;
-                if (i >= k) P[i + h * k] -= P[i + h * j] * P[k + h * j];
+            for (int j = 0; j < w; ++j) {
+                const double d = piv[j & 1];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    if (tid == 0) fail[cand] = b + 1;
+                    return;   // uniform: every thread read the same pivot
+                }
+                const double rd = sqrt(d);
+                const double inv = 1.0 / rd;
+                if (q == (j & 3)) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (q + 4 * t == j) {
+                            if (rl > j && rl < h) {
+                                a[t] *= inv;
+                                col[rl] = a[t];
+                            } else if (rl == j) {
+                                a[t] = rd;
+                            }
+                        }
+                }
+                __syncthreads();
+                if (rl > j && rl < h) {
+                    const double l = col[rl];
+                    const int kend = rl < w ? rl : w - 1;
+                    double cv[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) cv[t] = col[(q + 4 * t) & 31];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int k = q + 4 * t;
+                        const double lk = (k > j && k <= kend) ? l : 0.0;
+                        a[t] = fma(-lk, cv[t], a[t]);
+                    }
+                }
+                if (rl == j + 1 && q == ((j + 1) & 3)) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (q + 4 * t == j + 1) piv[(j + 1) & 1] = a[t];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = q + 4 * t;
+                if (rl < h && k < w && (rl >= w || k <= rl)) P[rl + h * k] = a[t];
             }
             __syncthreads();
+        } else {
+            // tall panels: entries stay in LDS; thread (row lane r, quarter q) updates
+            // rows r, r + 64, ... at columns j + 1 + q, j + 5 + q, ...
+            const int rl = tid & 63, q = tid >> 6;
+            for (int j = 0; j < w; ++j) {
+                const double d = P[j + h * j];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    if (tid == 0) fail[cand] = b + 1;
+                    return;
+                }
+                const double rd = sqrt(d);
+                const double inv = 1.0 / rd;
+                for (int k = j + 1 + tid; k < w; k += blockDim.x) colw[k] = P[k + h * j] * inv;
+                for (int i = j + 1 + tid; i < h; i += blockDim.x) P[i + h * j] *= inv;
+                __syncthreads();
+                if (tid == 0) P[j + h * j] = rd;
+                for (int i = j + 1 + rl; i < h; i += 64) {
+                    const double lij = P[i + h * j];
+                    const int kend = i < w ? i : w - 1;
+                    double v[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int k = j + 1 + q + 4 * t;
+                        v[t] = (k <= kend) ? P[i + h * k] : 0.0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int k = j + 1 + q + 4 * t;
+                        if (k <= kend) P[i + h * k] = v[t] - lij * colw[k];
+                    }
+                }
+                __syncthreads();
+            }
         }
         for (int i = tid; i < h * w; i += blockDim.x) L[off + i] = P[i];
         for (int64_t t = up_ptr[b] + tid; t < up_ptr[b + 1]; t += blockDim.x) {
@@ -130,94 +209,69 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
     }
 }
 
-// In-LDS Cholesky of the c x c lower triangle of A (column-major, ld c).
-// Returns false (uniformly) on a non-positive pivot.  blockDim = 64.
-__device__ bool lds_chol(double *A, int c) {
-    const int tid = threadIdx.x;
-    for (int j = 0; j < c; ++j) {
-        const double d = A[j + c * j];
-        if (!(d > 0.0) || !isfinite(d)) return false;
-        const double rd = sqrt(d);
-        const double inv = 1.0 / rd;
-        for (int i = j + 1 + tid; i < c; i += blockDim.x) A[i + c * j] *= inv;
-        __syncthreads();
-        if (tid == 0) A[j + c * j] = rd;
-        const int nk = c - j - 1;
-        for (int idx = tid; idx < nk * c; idx += blockDim.x) {
-            const int k = j + 1 + idx / c;
-            const int i = idx % c;
-            if (i >= k) A[i + c * k] -= A[i + c * j] * A[k + c * j];
-        }
-        __syncthreads();
-    }
-    return true;
-}
-
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
              const int *__restrict__ cl_map, const int *__restrict__ cl_first, const double *__restrict__ Xbar,
              double *__restrict__ Lhat, int *__restrict__ fail) {
-    extern __shared__ double sm[];
+    __shared__ CholLds sh;
     const int r = blockIdx.x;
     const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
     const int ns = cl_first[r + 1] - cl_first[r];
     const int *map = cl_map + cl_map_ptr[r];
-    double *Z = sm;          // c x c: P_r Xbar(C_r,C_r) P_r^T, then M_r
-    double *Mi = sm + c * c; // c x c: M_r^{-1}
-    const int tid = threadIdx.x;
-    // Step 2-1: Z(a, b) = Xbar(C[c-1-a], C[c-1-b]); packed lower index of (i, j), i >= j:
-    // j * (2c - j + 1) / 2 + (i - j)
-    for (int idx = tid; idx < c * c; idx += blockDim.x) {
-        const int a = idx % c, bb = idx / c;
-        if (a < bb) { Z[idx] = 0.0; continue; }
-        const int i = c - 1 - bb, j = c - 1 - a;   // original clique indices, i >= j
-        Z[idx] = Xbar[map[j * (2 * c - j + 1) / 2 + (i - j)]];
+    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
+    // packed lower index of clique entry (ii, jj), ii >= jj: jj * (2c - jj + 1) / 2 + (ii - jj)
+    auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
+    // Step 2-1: Z = P_r Xbar(C_r, C_r) P_r^T, Z(a, b) = Xbar(C[c-1-a], C[c-1-b])
+    double a[16], m[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = q + 4 * t;
+        a[t] = (i < c && k <= i) ? Xbar[map[pk(c - 1 - k, c - 1 - i)]] : 0.0;
+        m[t] = (k == i) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    // Step 2-2: Z = M_r M_r^T
-    if (!lds_chol(Z, c)) {
+    // Step 2-2: Z = M_r M_r^T, with M_r^{-1} alongside
+    int bad = 0;
+    if (!chol_reg<true>(a, m, c, sh, &bad)) {
         if (tid == 0) atomicCAS(fail, 0, r + 1);
         return;
     }
-    // M_r^{-1}, column k by forward substitution (threads over k)
-    for (int k = tid; k < c; k += blockDim.x) {
-        for (int i = 0; i < k; ++i) Mi[i + c * k] = 0.0;
-        Mi[k + c * k] = 1.0 / Z[k + c * k];
-        for (int i = k + 1; i < c; ++i) {
-            double acc = 0.0;
-            for (int j = k; j < i; ++j) acc += Z[i + c * j] * Mi[j + c * k];
-            Mi[i + c * k] = -acc / Z[i + c * i];
+    // Steps 2-3 and 3: L_r = P_r M_r^{-T} P_r^T, i.e. L_r(ii, jj) = M_r^{-1}(c-1-jj, c-1-ii);
+    // its first ns columns are Lhat(C_r, S_r).  This thread holds M_r^{-1}(i, k).
+    if (i < c && i >= c - ns) {
+        const int jj = c - 1 - i;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int k = q + 4 * t;
+            if (k <= i) Lhat[map[pk(c - 1 - k, jj)]] = m[t];
         }
     }
-    __syncthreads();
-    // Steps 2-3 and 3: L_r(i, j) = (P M^{-T} P)(i, j) = M^{-1}(c-1-j, c-1-i), first ns columns
-    for (int j = 0; j < ns; ++j)
-        for (int i = j + tid; i < c; i += blockDim.x)
-            Lhat[map[j * (2 * c - j + 1) / 2 + (i - j)]] = Mi[(c - 1 - j) + c * (c - 1 - i)];
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
            const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
            double *__restrict__ alpha_cl) {
-    extern __shared__ double A[];
+    __shared__ CholLds sh;
     const int r = blockIdx.x;
     const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
     const int *map = cl_map + cl_map_ptr[r];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
+    auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
+    // the clique block in the reversed order Algorithm 1 factorises in
+    double x[16], dx[16], a[16], unused[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int k = q + 4 * t;
+        const bool in = i < c && k <= i;
+        const int s = in ? map[pk(c - 1 - k, c - 1 - i)] : 0;
+        x[t] = in ? Xbar[s] : 0.0;
+        dx[t] = in ? dX[s] : 0.0;
+    }
     auto test = [&](double al) -> bool {
-        // reversed row/column order, the pivot order Algorithm 1 factorises in
-        for (int idx = tid; idx < c * c; idx += blockDim.x) {
-            const int a = idx % c, bb = idx / c;
-            if (a < bb) continue;
-            const int i = c - 1 - bb, j = c - 1 - a;
-            const int s = map[j * (2 * c - j + 1) / 2 + (i - j)];
-            A[idx] = Xbar[s] + al * dX[s];
-        }
-        __syncthreads();
-        const bool ok = lds_chol(A, c);
-        __syncthreads();
-        return ok;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) a[t] = fma(al, dx[t], x[t]);
+        int bad = 0;
+        return chol_reg<false>(a, unused, c, sh, &bad);
     };
     double res;
     if (test(1.0)) {
@@ -300,15 +354,13 @@ void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, h
 }
 
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail, hipStream_t st) {
-    const size_t lds = size_t(2) * d.max_clique * d.max_clique * sizeof(double);
-    hipLaunchKernelGGL(k_algorithm1, dim3(d.ncl), dim3(64), lds, st, d.cl_ptr, d.cl_map_ptr, d.cl_map,
+    hipLaunchKernelGGL(k_algorithm1, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map,
                        d.cl_first, Xbar, Lhat, fail);
 }
 
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX, double *alpha_cl,
                           double *out, hipStream_t st) {
-    const size_t lds = size_t(d.max_clique) * d.max_clique * sizeof(double);
-    hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(64), lds, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
+    hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
                        alpha_cl);
     hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, alpha_cl, out);
 }

@@ -124,6 +124,146 @@ k_dX(int64_t nslot, int n, const int *__restrict__ slot_row, const int *__restri
     }
 }
 
+// Z = X^ M, column-major (Z(p, c) at p + n c); the entries of column c of M are
+// uniform across the workgroup, the reads of X^ are coalesced over p
+__global__ void __launch_bounds__(256)
+k_zcol(int n, const int64_t *__restrict__ cptr, const int *__restrict__ rows, const int *__restrict__ slots,
+       const double *__restrict__ Mvec, const double *__restrict__ Xh, double *__restrict__ Z) {
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        const int64_t t0 = cptr[c], t1 = cptr[c + 1];
+        for (int p = threadIdx.x; p < n; p += blockDim.x) {
+            double s = 0.0;
+            for (int64_t t = t0; t < t1; ++t) s += Mvec[slots[t]] * Xh[p + int64_t(n) * rows[t]];
+            Z[p + int64_t(n) * c] = s;
+        }
+    }
+}
+
+// Max-cut form: h_p = A_p . (X^ M Y^{-1}) = (X^ M Y^{-1})(p, p) = sum_c (X^ M)(p, c) Y^{-1}(p, c)
+// (Y^{-1} symmetric).  Partial sums over chunks of CW columns; X^ M is never stored.
+constexpr int kRhsCW = 32;
+__global__ void __launch_bounds__(256)
+k_rhs_had_partial(int n, const int64_t *__restrict__ cptr, const int *__restrict__ rows,
+                  const int *__restrict__ slots, const double *__restrict__ Mvec, const double *__restrict__ Xh,
+                  const double *__restrict__ Yi, double *__restrict__ part) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c0 = blockIdx.y * kRhsCW;
+    const int c1 = min(n, c0 + kRhsCW);
+    if (p >= n) return;
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        double z = 0.0;
+        for (int64_t t = cptr[c]; t < cptr[c + 1]; ++t) z += Mvec[slots[t]] * Xh[p + int64_t(n) * rows[t]];
+        acc += z * Yi[p + int64_t(n) * c];
+    }
+    part[int64_t(blockIdx.y) * n + p] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_sum_partials(int n, int nparts, const double *__restrict__ part, const int *__restrict__ pos,
+               double *__restrict__ out) {
+    // out[k] = sum over parts of part[., pos[k]] (pos maps constraint k to its position)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int p = pos ? pos[k] : k;
+        double s = 0.0;
+        for (int c = 0; c < nparts; ++c) s += part[int64_t(c) * n + p];
+        out[k] = s;
+    }
+}
+
+// dX on E, block-tiled: for storage block b and a chunk of d, partial sums of
+// T(R_b, cols_b) = Z(R_b, :) Y^{-1}(:, cols_b) and T(cols_b, R_b) with T = X^ dY Y^{-1}
+// (Z = X^ dY column-major).  part holds [chunk][2][nslot].
+constexpr int kDxTile = 32;
+constexpr int kDxRows = 64;
+__global__ void __launch_bounds__(256)
+k_dX_block(int n, int nslot_i, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+           const int *__restrict__ bl_rows, const int64_t *__restrict__ bl_off, const double *__restrict__ Z,
+           const double *__restrict__ Yi, int dchunk, double *__restrict__ part) {
+    __shared__ double Zr[kDxRows * (kDxTile + 1)];   // rows x tile
+    __shared__ double Yr[kDxTile * (kDxRows + 1)];   // tile x rows
+    __shared__ double Zc[32 * (kDxTile + 1)];        // w x tile
+    __shared__ double Yc[kDxTile * 33];              // tile x w
+    const int b = blockIdx.x, ch = blockIdx.y;
+    const int F = bl_first[b], w = bl_first[b + 1] - F;
+    const int64_t r0 = bl_rptr[b];
+    const int h = int(bl_rptr[b + 1] - r0);
+    const int *R = bl_rows + r0;
+    const int tid = threadIdx.x;
+    const int64_t off = bl_off[b];
+    double *p1 = part + int64_t(ch) * 2 * nslot_i;
+    double *p2 = p1 + nslot_i;
+    const int d_begin = ch * dchunk, d_end = min(n, d_begin + dchunk);
+    for (int pt = 0; pt < h; pt += kDxRows) {          // row tiles
+        const int hh = min(kDxRows, h - pt);
+        const int nout = hh * w;                       // <= 64 x 32: 8 outputs per thread
+        double a1[8], a2[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a1[t] = a2[t] = 0.0;
+        for (int d0 = d_begin; d0 < d_end; d0 += kDxTile) {
+            const int nd = min(kDxTile, d_end - d0);
+            for (int idx = tid; idx < kDxRows * kDxTile; idx += blockDim.x) {
+                const int p = idx % kDxRows, dd = idx / kDxRows;
+                Zr[p * (kDxTile + 1) + dd] = (dd < nd && p < hh) ? Z[R[pt + p] + int64_t(n) * (d0 + dd)] : 0.0;
+            }
+            for (int idx = tid; idx < kDxRows * kDxTile; idx += blockDim.x) {
+                const int dd = idx % kDxTile, p = idx / kDxTile;
+                Yr[dd * (kDxRows + 1) + p] = (dd < nd && p < hh) ? Yi[(d0 + dd) + int64_t(n) * R[pt + p]] : 0.0;
+            }
+            for (int idx = tid; idx < 32 * kDxTile; idx += blockDim.x) {
+                const int c = idx % 32, dd = idx / 32;
+                Zc[c * (kDxTile + 1) + dd] = (dd < nd && c < w) ? Z[(F + c) + int64_t(n) * (d0 + dd)] : 0.0;
+            }
+            for (int idx = tid; idx < 32 * kDxTile; idx += blockDim.x) {
+                const int dd = idx % kDxTile, c = idx / kDxTile;
+                Yc[dd * 33 + c] = (dd < nd && c < w) ? Yi[(d0 + dd) + int64_t(n) * (F + c)] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int o = tid + 256 * t;
+                const int p = o % kDxRows, c = o / kDxRows;   // c < 32 always
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll 8
+                for (int dd = 0; dd < kDxTile; ++dd) {
+                    s1 += Zr[p * (kDxTile + 1) + dd] * Yc[dd * 33 + c];
+                    s2 += Zc[c * (kDxTile + 1) + dd] * Yr[dd * (kDxRows + 1) + p];
+                }
+                a1[t] += s1;
+                a2[t] += s2;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int o = tid + 256 * t;
+            const int p = o % kDxRows, c = o / kDxRows;
+            if (p < hh && c < w) {
+                const int64_t sl = off + (pt + p) + int64_t(h) * c;
+                p1[sl] = a1[t];
+                p2[sl] = a2[t];
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_dX_finish(int64_t nslot, int n, int nch, const int *__restrict__ slot_row, const int *__restrict__ slot_col,
+            const double *__restrict__ part, const double *__restrict__ Yi, const double *__restrict__ Xbar,
+            double beta_mu, double *__restrict__ dX) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot; s += int64_t(gridDim.x) * blockDim.x) {
+        const int i = slot_row[s];
+        if (i < 0) {
+            dX[s] = 0.0;
+            continue;
+        }
+        const int j = slot_col[s];
+        double t = 0.0;
+        for (int c = 0; c < nch; ++c) t += part[(2 * c) * nslot + s] + part[(2 * c + 1) * nslot + s];
+        dX[s] = beta_mu * Yi[i + int64_t(n) * j] - Xbar[s] - 0.5 * t;
+    }
+}
+
 __global__ void k_fill(int len, double v, double *__restrict__ x) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) x[i] = v;
 }
@@ -177,6 +317,33 @@ void launch_scm_general(const DevStruct &d, const int64_t *kq_ptr_host, const do
         hipLaunchKernelGGL(k_contract, dim3(grid_cap(d.m - q, 256)), dim3(256), 0, st, d.m, q, d.am_ptr,
                            d.am_sidx, d.am_val, T, B + ldb * q);
     }
+}
+
+void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, double *Z, hipStream_t st) {
+    hipLaunchKernelGGL(k_zcol, dim3(grid_cap(d.n, 1)), dim3(256), 0, st, d.n, d.ag_cptr, d.ag_row, d.ag_slot, Mvec,
+                       Xh, Z);
+}
+
+int rhs_had_parts(const DevStruct &d) { return (d.n + kRhsCW - 1) / kRhsCW; }
+
+void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *Xh, const double *Yi, double *part,
+                         double *hcol, hipStream_t st) {
+    const int nparts = rhs_had_parts(d);
+    hipLaunchKernelGGL(k_rhs_had_partial, dim3((d.n + 255) / 256, nparts), dim3(256), 0, st, d.n, d.ag_cptr,
+                       d.ag_row, d.ag_slot, Mvec, Xh, Yi, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(grid_cap(d.m, 256)), dim3(256), 0, st, d.m, nparts,
+                       (const double *)part, d.had_pos, hcol);
+}
+
+int dX_chunks(const DevStruct &d) { return (d.n + 255) / 256; }
+
+void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, const double *Xbar, double beta_mu,
+                       double *part, double *dX, hipStream_t st) {
+    const int nch = dX_chunks(d);
+    hipLaunchKernelGGL(k_dX_block, dim3(d.nb, nch), dim3(256), 0, st, d.n, int(d.nslot), d.bl_first, d.bl_rptr,
+                       d.bl_rows, d.bl_off, Z, Yi, 256, part);
+    hipLaunchKernelGGL(k_dX_finish, dim3(grid_cap(d.nslot, 256)), dim3(256), 0, st, d.nslot, d.n, nch, d.slot_row,
+                       d.slot_col, (const double *)part, Yi, Xbar, beta_mu, dX);
 }
 
 void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g, hipStream_t st) {

@@ -61,8 +61,8 @@ k_inv_solve(int n, int nb, int maxw, const int *__restrict__ bl_first, const int
         const int h = int(bl_rptr[b + 1] - r0);
         const double *P = L + bl_off[b];
         const double *D = Dinv + bl_dinv[b];
-        for (int i = tid; i < h * w; i += kThreads) Pn[i] = P[i];
-        for (int i = tid; i < w * w; i += kThreads) Dn[i] = D[i];
+        stage_lds<8>(Pn, P, h * w);
+        stage_lds<4>(Dn, D, w * w);
         for (int i = tr; i < w; i += RG) {
             const int fs = bl_fslot[r0 + i];
             double val = 0.0;
@@ -98,8 +98,8 @@ k_inv_solve(int n, int nb, int maxw, const int *__restrict__ bl_first, const int
         const int h = int(bl_rptr[b + 1] - r0);
         const double *P = L + bl_off[b];
         const double *D = Dinv + bl_dinv[b];
-        for (int i = tid; i < h * w; i += kThreads) Pn[i] = P[i];
-        for (int i = tid; i < w * w; i += kThreads) Dn[i] = D[i];
+        stage_lds<8>(Pn, P, h * w);
+        stage_lds<4>(Dn, D, w * w);
         __syncthreads();
         for (int j = tr; j < w; j += RG) {
             double s = (fwd_active && colok) ? outc[F + j] : 0.0;

@@ -69,17 +69,15 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
     const int t = threadIdx.x;
     double pobj = 0.0, bz = 0.0, rmax = 0.0, gmax = 0.0, xy = 0.0;
     bool bad = false;
-    for (int k = t; k <= m; k += blockDim.x) {
+    // A_0 . X over all threads (A_0 carries the whole aggregate pattern)
+    for (int64_t e = con_ptr[0] + t; e < con_ptr[1]; e += blockDim.x) pobj += con_val[e] * X[con_slot[e]];
+    for (int k = 1 + t; k <= m; k += blockDim.x) {
         double a = 0.0;
         for (int64_t e = con_ptr[k]; e < con_ptr[k + 1]; ++e) a += con_val[e] * X[con_slot[e]];
-        if (k == 0) {
-            pobj = a;
-        } else {
-            const double r = b[k - 1] - a;
-            rmax = fmax(rmax, fabs(r));
-            bz += b[k - 1] * z[k - 1];
-            bad |= !isfinite(z[k - 1]);
-        }
+        const double r = b[k - 1] - a;
+        rmax = fmax(rmax, fabs(r));
+        bz += b[k - 1] * z[k - 1];
+        bad |= !isfinite(z[k - 1]);
     }
     for (int64_t s = t; s < nslot; s += blockDim.x) {
         const double w = wE[s];

@@ -12,6 +12,25 @@
 
 namespace sdpc {
 
+// Copy count doubles from global memory to LDS, issuing U loads per thread before
+// any LDS store so that the loads overlap instead of waiting one by one.
+template <int U = 8>
+__device__ inline void stage_lds(double *dst, const double *__restrict__ src, int count) {
+    for (int base = threadIdx.x; base < count; base += U * blockDim.x) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * blockDim.x;
+            v[u] = i < count ? src[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * blockDim.x;
+            if (i < count) dst[i] = v[u];
+        }
+    }
+}
+
 struct DevStruct {
     int n = 0, m = 0, nb = 0, ncl = 0;
     int64_t nslot = 0;
@@ -125,14 +144,31 @@ void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double be
 // dX on E:  beta mu Y^{-1} - Xbar - sym(X^ dY Y^{-1}) with W = X^ dY (row-major)
 void launch_dX(const DevStruct &d, const double *W, const double *Yi, const double *Xbar,
                double beta_mu, double *dX, hipStream_t st);
+// Z = X^ M column-major (n x n) for M on the aggregate pattern (E-vector)
+void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, double *Z, hipStream_t st);
+// max-cut form of the extra column: hcol[k] = (X^ M Y^{-1})(a_k, a_k); part: rhs_had_parts x n
+int rhs_had_parts(const DevStruct &d);
+void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *Xh, const double *Yi,
+                         double *part, double *hcol, hipStream_t st);
+// dX on E from Z = X^ dY (column-major): part holds 2 * dX_chunks * nslot doubles
+int dX_chunks(const DevStruct &d);
+void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, const double *Xbar,
+                       double beta_mu, double *part, double *dX, hipStream_t st);
 // W = X^ M (row-major n x n) for M on the aggregate pattern (E-vector)
 void launch_dense_times_agg(const DevStruct &d, const double *Xh, const double *Mvec, double *W,
                             hipStream_t st);
 
 // ---- dense FP64 Cholesky and SCE solve (k_dense.hip)
 void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
+// the same with rows m..rows-1 riding along (e.g. g^T as row m yields R^{-1} g there)
+void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *fail,
+                       hipStream_t st);
 void launch_potrs(int m, const double *R, int64_t ldb, const double *dinv, const double *g,
                   double *y, double *x, hipStream_t st);
+// backward substitution R^T x = u (u read with stride ustride); y is workspace
+void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *dinv, const double *u,
+                      int64_t ustride, double *y, double *x, hipStream_t st);
+void launch_set_row(int m, const double *g, double *row, int64_t stride, hipStream_t st);
 size_t potrf_work_doubles(int m);
 
 }  // namespace sdpc

@@ -52,7 +52,8 @@ class sdpc_result(C.Structure):
                 ("rel_gap", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double), ("mu", C.c_double),
                 ("alpha_p", C.c_double), ("alpha_d", C.c_double), ("beta", C.c_double),
                 ("t_scm_ms", C.c_double), ("t_chol_ms", C.c_double), ("t_pmatrix_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("device_bytes", C.c_size_t)]
+                ("t_total_ms", C.c_double), ("t_potrf_ms", C.c_double), ("n_potrf", C.c_int32),
+                ("pad_", C.c_int32), ("device_bytes", C.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -31,7 +31,14 @@ def run(name, prob, gap):
                relgap=res["relgap"], pinf=res["pinf"], dinf=res["dinf"],
                z=res["z"].tolist(), seconds=time.time() - t0,
                t_scm=[h.get("t_scm") for h in res["history"] if "t_scm" in h],
-               t_iter=[h.get("t_iter") for h in res["history"] if "t_iter" in h])
+               t_iter=[h.get("t_iter") for h in res["history"] if "t_iter" in h],
+               history=[{k: h[k] for k in ("it", "pobj", "dobj", "relgap", "pinf", "dinf")}
+                        for h in res["history"]])
+    # iterations the same run needed to pass the default stopping test (gap and
+    # infeasibilities <= 1e-7): the iteration count of a solve at gap 1e-7
+    out["iters_to_1e-7"] = next((h["it"] for h in res["history"]
+                                 if h["relgap"] <= 1e-7 and h["pinf"] <= 1e-7 and h["dinf"] <= 1e-7),
+                                None)
     # also the trajectory at the default tolerance, for iteration counts
     with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
         json.dump(out, f)
