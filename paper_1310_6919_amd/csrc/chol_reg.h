@@ -1,100 +1,144 @@
-// Register-resident Cholesky of a small symmetric matrix (order c <= 64) by one
-// 256-thread workgroup, shared by the dense SCM diagonal blocks, Algorithm 1
-// and the clique-wise step-length test.
+// Register-tiled Cholesky of a small matrix by one 256-thread workgroup, shared by
+// the diagonal blocks of the dense SCM Cholesky, Algorithm 1, the clique-wise
+// step-length test and the supernodal panels of Y = N N^T.
 //
-// Thread (i, q) = (tid / 4, tid % 4) holds row i at columns q, q + 4, ..., q + 60
-// in a[0..15] (entries above the diagonal are zero).  Only the scaled pivot
-// column (colc), the finished row of L^{-1} (rowc) and the next pivot (piv)
-// pass through LDS.  Every LDS value a step needs is read before any update, and
-// the updates are masked multiply-adds, so the LDS latency is paid once per step
-// instead of once per element.
+// Thread t owns a TR x TC tile of the (NR x NC) working matrix, NR = (256 / JG) TR,
+// NC = JG TC: rows i0 = TR (t / JG) + [0, TR), columns j0 = TC (t % JG) + [0, TC).
+// Right-looking elimination, one pivot per step and one barrier per step:
+//   * column k of the partially updated matrix (unscaled, zero above row k) and,
+//     for the inverse, row k of the partially eliminated identity, sit in a
+//     double-buffered LDS slot, written at the end of step k - 1 by the threads
+//     that own them;
+//   * every thread reads the pivot d = A(k, k), forms 1/sqrt(d) itself, scales
+//     the few column / row values it needs and applies the rank-one update to its
+//     whole tile.  Rows above k read zeros; the pivot column and the pivot row
+//     are given a zero multiplier and scaled in place instead, so when the loop
+//     ends the tiles hold L (lower triangle) and L^{-1} exactly, and nothing has
+//     to leave the registers during the elimination.
+// The pivot loop is unrolled by TC so every register index is a constant.
+// Entries beyond the active order must be padded with the identity (square use)
+// or zeros (panel rows), so that padded pivots are 1 and change nothing.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace sdpc {
 
 // 1/sqrt(d) from the hardware estimate refined by two Newton steps
-// (y <- y (3 - d y^2) / 2), and sqrt(d) = d / sqrt(d); a short dependent chain
-// compared with a correctly rounded square root followed by a division.
-__device__ inline void rsqrt_pivot(double d, double &rd, double &inv) {
+// (y <- y (3 - d y^2) / 2); sqrt(d) is then d / sqrt(d).  A short dependent
+// chain compared with a correctly rounded square root followed by a division.
+__device__ inline double rsqrt_newton(double d) {
     double y = __builtin_amdgcn_rsq(d);
     y = y * fma(-0.5 * d, y * y, 1.5);
     y = y * fma(-0.5 * d, y * y, 1.5);
-    inv = y;
-    rd = d * y;
+    return y;
 }
 
-struct CholLds {
-    double colc[64];
-    double rowc[64];
-    double piv[2];
+template <int NR, int NC>
+struct TileLds {
+    double col[2][NR];   // column k of the working matrix (unscaled), rows 0..NR-1
+    double row[2][NC];   // row k of the partially eliminated identity
 };
 
-// Factorises in place: on success a[] holds L (A = L L^T) and, when INV, r[]
-// holds L^{-1} (r must start as the identity rows).  Returns false (uniformly
-// across the workgroup) when a pivot is not positive; *bad_pivot gets its index.
-template <bool INV>
-__device__ inline bool chol_reg(double a[16], double r[16], int c, CholLds &sh, int *bad_pivot) {
-    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
-    if (tid == 0) sh.piv[0] = a[0];
-    __syncthreads();
-    for (int k = 0; k < c; ++k) {
-        const double d = sh.piv[k & 1];
-        if (!(d > 0.0) || !isfinite(d)) {
-            *bad_pivot = k;
-            return false;   // uniform: every thread read the same pivot
-        }
-        double rd, inv;
-        rsqrt_pivot(d, rd, inv);
-        // column k: owners scale their entry below the pivot and publish it
-        if (q == (k & 3)) {
-            const int tk = k >> 2;
+// Loads TC consecutive doubles from LDS with 16-byte reads (TC even, aligned).
+template <int N>
+__device__ inline void lds_vec(const double *p, double (&v)[N]) {
+    static_assert(N % 2 == 0, "even vector length");
 #pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (t == tk) {
-                    if (i > k && i < c) {
-                        a[t] *= inv;
-                        sh.colc[i] = a[t];
-                    } else if (i == k) {
-                        a[t] = rd;
+    for (int u = 0; u < N; u += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(p + u);
+        v[u] = t.x;
+        v[u + 1] = t.y;
+    }
+}
+
+// Factorises the leading ncol columns.  a[][] holds the tile of the symmetric
+// input (lower triangle; entries above it end up meaningless); with INV, r[][]
+// must hold the tile of the identity.  On success a[][] holds the tile of L in
+// its lower triangle (columns < ncol) and, with INV, r[][] the tile of L^{-1}.
+// Returns false, uniformly, if a pivot is not positive and finite; *bad_pivot is
+// its index.
+template <int TR, int TC, int JG, bool INV>
+__device__ inline bool chol_tile(double (&a)[TR][TC], double (&r)[TR][TC], int ncol,
+                                 TileLds<(256 / JG) * TR, JG * TC> &sh, int *bad_pivot) {
+    static_assert(!INV || TR == TC, "the inverse needs square tiles");
+    static_assert(TC % TR == 0, "pivot rows must stay aligned with the unrolled columns");
+    const int tid = threadIdx.x;
+    const int ig = tid / JG, jg = tid % JG;
+    const int i0 = TR * ig, j0 = TC * jg;
+    __syncthreads();   // a previous call on the same buffers may still be reading them
+    // publish column 0 and row 0 of the identity
+    if (jg == 0) {
+#pragma unroll
+        for (int u = 0; u < TR; ++u) sh.col[0][i0 + u] = a[u][0];
+    }
+    if (INV && ig == 0) {
+#pragma unroll
+        for (int v = 0; v < TC; ++v) sh.row[0][j0 + v] = r[0][v];
+    }
+    __syncthreads();
+    const int nkb = (ncol + TC - 1) / TC;
+    for (int kb = 0; kb < nkb; ++kb) {
+#pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            const int k = TC * kb + c;
+            if (k < ncol) {   // uniform
+                const double *cb = sh.col[k & 1];
+                const double d = cb[k];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    *bad_pivot = k;
+                    return false;   // uniform: every thread read the same pivot
+                }
+                const double inv = rsqrt_newton(d);
+                double li[TR], lj[TC], rk[TC];
+                lds_vec(cb + i0, li);
+                lds_vec(cb + j0, lj);
+                if (INV) lds_vec(sh.row[k & 1] + j0, rk);
+                // the pivot row (row group k / TR, row c % TR) and the pivot column
+                // (column group kb, column c) take no update; they are scaled below
+                const int cr = c % TR;   // constants once the loop over c is unrolled
+                const bool prow = (ig == k / TR), pcol = (jg == kb);
+#pragma unroll
+                for (int u = 0; u < TR; ++u) li[u] = (u == cr && prow) ? 0.0 : li[u] * inv;
+#pragma unroll
+                for (int v = 0; v < TC; ++v) lj[v] = (v == c && pcol) ? 0.0 : lj[v] * inv;
+                if (INV) {
+#pragma unroll
+                    for (int v = 0; v < TC; ++v) rk[v] *= inv;
+                }
+#pragma unroll
+                for (int u = 0; u < TR; ++u)
+#pragma unroll
+                    for (int v = 0; v < TC; ++v) a[u][v] = fma(-li[u], lj[v], a[u][v]);
+                if (INV) {
+#pragma unroll
+                    for (int u = 0; u < TR; ++u)
+#pragma unroll
+                        for (int v = 0; v < TC; ++v) r[u][v] = fma(-li[u], rk[v], r[u][v]);
+                }
+                if (pcol) {   // column k of L (rows at and below k; zeros above)
+#pragma unroll
+                    for (int u = 0; u < TR; ++u) a[u][c] *= inv;
+                }
+                if (INV && prow) {   // row k of L^{-1}
+#pragma unroll
+                    for (int v = 0; v < TC; ++v) r[cr][v] *= inv;
+                }
+                // publish column k + 1 (rows above it zero) and row k + 1 of the inverse
+                const int k1 = k + 1;
+                const int cn = (c + 1) % TC;
+                if (k1 < ncol) {
+                    if (jg == k1 / TC) {
+#pragma unroll
+                        for (int u = 0; u < TR; ++u) sh.col[k1 & 1][i0 + u] = (i0 + u >= k1) ? a[u][cn] : 0.0;
+                    }
+                    if (INV && ig == k1 / TR) {
+#pragma unroll
+                        for (int v = 0; v < TC; ++v) sh.row[k1 & 1][j0 + v] = r[cn % TR][v];
                     }
                 }
-        }
-        if (INV && i == k) {
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const double v = r[t] * inv;   // row k of L^{-1} is final
-                r[t] = (q + 4 * t <= k) ? v : r[t];
-                if (q + 4 * t <= k) sh.rowc[q + 4 * t] = v;
+                __syncthreads();
             }
         }
-        __syncthreads();
-        if (i > k && i < c) {
-            const double l = sh.colc[i];
-            double cv[16], rv[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                cv[t] = sh.colc[q + 4 * t];
-                if (INV) rv[t] = sh.rowc[q + 4 * t];
-            }
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int kk = q + 4 * t;
-                const double la = (kk > k && kk <= i) ? l : 0.0;
-                a[t] = fma(-la, cv[t], a[t]);
-                if (INV) {
-                    const double lr = (kk <= k) ? l : 0.0;
-                    r[t] = fma(-lr, rv[t], r[t]);
-                }
-            }
-        }
-        if (i == k + 1 && q == ((k + 1) & 3)) {
-            const int tk = (k + 1) >> 2;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (t == tk) sh.piv[(k + 1) & 1] = a[t];
-        }
-        __syncthreads();
     }
     return true;
 }

@@ -70,26 +70,33 @@ __device__ inline void load_tile(double *S, const double *M, int64_t ld, int r0,
 
 __global__ void __launch_bounds__(256)
 k_potrf_diag(double *__restrict__ B, int64_t ldb, int j, int jb, double *__restrict__ Linv, int *__restrict__ fail) {
-    __shared__ CholLds sh;
-    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
-    double a[16], r[16];
+    __shared__ TileLds<64, 64> sh;
+    const int tid = threadIdx.x;
+    const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
+    double a[4][4], r[4][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int k = q + 4 * t;
-        a[t] = (i < jb && k <= i) ? B[(j + i) + ldb * (j + k)] : 0.0;
-        r[t] = (k == i) ? 1.0 : 0.0;
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            a[u][v] = (i < jb && k <= i) ? B[(j + i) + ldb * (j + k)] : (i == k ? 1.0 : 0.0);
+            r[u][v] = (i == k) ? 1.0 : 0.0;
+        }
     int bad = 0;
-    if (!chol_reg<true>(a, r, jb, sh, &bad)) {
+    if (!chol_tile<4, 4, 16, true>(a, r, jb, sh, &bad)) {
         if (tid == 0) atomicCAS(fail, 0, j + bad + 1);
         return;
     }
+    // the factor back into the lower part of the block, its inverse into Linv
+    // (column-major 64 x 64, zero beyond the block)
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int k = q + 4 * t;
-        if (i < jb && k <= i) B[(j + i) + ldb * (j + k)] = a[t];
-        Linv[i + NB * k] = (i < jb && k < jb) ? r[t] : 0.0;   // column-major 64 x 64
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            if (i < jb && k <= i) B[(j + i) + ldb * (j + k)] = a[u][v];
+            Linv[i + NB * k] = (i < jb && k < jb) ? r[u][v] : 0.0;
+        }
 }
 
 __global__ void __launch_bounds__(256)

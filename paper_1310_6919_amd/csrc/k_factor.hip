@@ -26,6 +26,15 @@ namespace {
 
 constexpr int kCholThreads = 256;
 
+// Candidate step length of the dual positive-definiteness test: round 0 is a
+// logarithmic grid 1e-8 .. 1; later rounds are an even grid inside the bracket
+// (lo, hi) left by the previous round.
+__device__ inline double cand_alpha(int cand, int K, int round, const double *bracket) {
+    if (round == 0) return pow(10.0, -8.0 * double(K - 1 - cand) / double(K - 1));
+    return bracket[0] + (bracket[1] - bracket[0]) * double(cand + 1) / double(K + 1);
+}
+
+
 __global__ void __launch_bounds__(kCholThreads)
 k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
           const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
@@ -33,30 +42,24 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
           const double *__restrict__ dY, const double *__restrict__ bracket, int round, double *__restrict__ Lbase,
           int64_t stride, int *__restrict__ fail) {
     extern __shared__ double P[];
-    __shared__ double col[64];   // scaled pivot column of a panel with at most 64 rows
+    __shared__ TileLds<64, 32> tsh;   // pivot columns of a panel with at most 64 rows
     __shared__ double colw[32];  // scaled pivot column (block width <= 32), tall panels
-    __shared__ double piv[2];
     const int tid = threadIdx.x;
     const int cand = blockIdx.x;
     double *L = Lbase + cand * stride;
-    double a = 0.0;
+    double al = 0.0;
     if (dY) {
         // round 0: a logarithmic grid 1e-8 .. 1; later rounds: an even grid inside
         // the bracket (lo, hi) left by the previous round (bracket[2] != 0: settled)
-        const int K = gridDim.x;
-        if (round == 0) {
-            a = pow(10.0, -8.0 * double(K - 1 - cand) / double(K - 1));
-        } else {
-            if (bracket[2] != 0.0) {
-                if (tid == 0) fail[cand] = 0;
-                return;
-            }
-            a = bracket[0] + (bracket[1] - bracket[0]) * double(cand + 1) / double(K + 1);
+        if (round > 0 && bracket[2] != 0.0) {
+            if (tid == 0) fail[cand] = 0;
+            return;
         }
+        al = cand_alpha(cand, gridDim.x, round, bracket);
     }
     // padding slots of the inputs are ignored (the factor stores an exact zero there)
     for (int64_t s = tid; s < nslot; s += blockDim.x)
-        L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? (Y[s] + a * dY[s]) : Y[s]);
+        L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? fma(al, dY[s], Y[s]) : Y[s]);
     __threadfence_block();
     __syncthreads();
     for (int b = 0; b < nb; ++b) {
@@ -68,63 +71,30 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
         __syncthreads();
         // right-looking factorisation of the panel
         if (h <= 64) {
-            // thread (row rl, quarter q) keeps P(rl, q + 4t) in registers; only the
-            // scaled pivot column (col) and the next pivot (piv) go through LDS
-            const int rl = tid & 63, q = tid >> 6;
-            double a[8];
+            // panel in registers: thread tiles of 2 rows x 4 columns over 64 x 32,
+            // zeros outside the panel; the factor goes back into P
+            const int i0 = 2 * (tid / 8), j0 = 4 * (tid % 8);
+            double a[2][4], unused[2][4];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int k = q + 4 * t;
-                a[t] = (rl < h && k < w && (rl >= w || k <= rl)) ? P[rl + h * k] : 0.0;
-            }
-            if (tid == 0) piv[0] = P[0];
-            __syncthreads();
-            for (int j = 0; j < w; ++j) {
-                const double d = piv[j & 1];
-                if (!(d > 0.0) || !isfinite(d)) {
-                    if (tid == 0) fail[cand] = b + 1;
-                    return;   // uniform: every thread read the same pivot
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, k = j0 + v;
+                    a[u][v] = (i < h && k < w && (i >= w || k <= i)) ? P[i + h * k] : 0.0;
+                    unused[u][v] = 0.0;
                 }
-                const double rd = sqrt(d);
-                const double inv = 1.0 / rd;
-                if (q == (j & 3)) {
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (q + 4 * t == j) {
-                            if (rl > j && rl < h) {
-                                a[t] *= inv;
-                                col[rl] = a[t];
-                            } else if (rl == j) {
-                                a[t] = rd;
-                            }
-                        }
-                }
-                __syncthreads();
-                if (rl > j && rl < h) {
-                    const double l = col[rl];
-                    const int kend = rl < w ? rl : w - 1;
-                    double cv[8];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) cv[t] = col[(q + 4 * t) & 31];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        const int k = q + 4 * t;
-                        const double lk = (k > j && k <= kend) ? l : 0.0;
-                        a[t] = fma(-lk, cv[t], a[t]);
-                    }
-                }
-                if (rl == j + 1 && q == ((j + 1) & 3)) {
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (q + 4 * t == j + 1) piv[(j + 1) & 1] = a[t];
-                }
-                __syncthreads();
+            int bad = 0;
+            if (!chol_tile<2, 4, 8, false>(a, unused, w, tsh, &bad)) {
+                if (tid == 0) fail[cand] = b + 1;
+                return;   // uniform
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int k = q + 4 * t;
-                if (rl < h && k < w && (rl >= w || k <= rl)) P[rl + h * k] = a[t];
-            }
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u, k = j0 + v;
+                    if (i < h && k < w && (i >= w || k <= i)) P[i + h * k] = a[u][v];
+                }
             __syncthreads();
         } else {
             // tall panels: entries stay in LDS; thread (row lane r, quarter q) updates
@@ -176,6 +146,120 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
     if (tid == 0) fail[cand] = 0;
 }
 
+// L_c = Y + alpha_c dY on the slots of E (zero in padding slots), one
+// candidate per blockIdx.y; with dY == nullptr a single copy of Y.
+__global__ void __launch_bounds__(256)
+k_cand_init(int64_t nslot, const double *__restrict__ wE, const double *__restrict__ Y,
+            const double *__restrict__ dY, const double *__restrict__ bracket, int round,
+            double *__restrict__ Lbase, int64_t stride) {
+    const int cand = blockIdx.y;
+    if (dY && round > 0 && bracket[2] != 0.0) return;   // settled: nothing to test
+    const double al = dY ? cand_alpha(cand, gridDim.y, round, bracket) : 0.0;
+    double *L = Lbase + cand * stride;
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot; s += int64_t(gridDim.x) * blockDim.x)
+        L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? fma(al, dY[s], Y[s]) : Y[s]);
+}
+
+__device__ inline double lane_bcast(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Y = N N^T on the storage blocks by a single wave (panels of at most 64 rows and
+// 32 columns).  Lane i holds row i of the panel in registers; the pivot and the
+// scaled pivot column reach the other lanes through readlane, so the elimination
+// needs neither LDS nor barriers.  The update of the ancestors, N(U, U) -=
+// L21 L21^T, takes its operands from LDS (rows of L21, row-major) and its old
+// values are loaded before the elimination so their latency is hidden.
+// blockIdx.x selects the candidate matrix L_c prepared by k_cand_init; the
+// factor overwrites it.
+constexpr int kPrefetch = 4;   // update pairs per lane loaded ahead of the elimination
+
+__global__ void __launch_bounds__(64)
+k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+               const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
+               const int *__restrict__ up_pair, const int *__restrict__ up_slot, const double *__restrict__ bracket,
+               int round, double *__restrict__ Lbase, int64_t stride, int *__restrict__ fail) {
+    extern __shared__ double Pr[];   // rows >= w of the factored panel, 32 doubles per row
+    const int lane = threadIdx.x;
+    const int cand = blockIdx.x;
+    if (bracket && round > 0 && bracket[2] != 0.0) {
+        if (lane == 0) fail[cand] = 0;
+        return;
+    }
+    double *L = Lbase + cand * stride;
+    for (int b = 0; b < nb; ++b) {
+        const int w = bl_first[b + 1] - bl_first[b];
+        const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
+        const int64_t off = bl_off[b];
+        const int64_t p0 = up_ptr[b];
+        const int np = int(up_ptr[b + 1] - p0);
+        int ps[kPrefetch], pp[kPrefetch];
+        double old[kPrefetch];
+#pragma unroll
+        for (int m = 0; m < kPrefetch; ++m) {
+            const int t = lane + 64 * m;
+            ps[m] = (t < np) ? up_slot[p0 + t] : -1;
+            pp[m] = (t < np) ? up_pair[p0 + t] : 0;
+        }
+#pragma unroll
+        for (int m = 0; m < kPrefetch; ++m) old[m] = (ps[m] >= 0) ? L[ps[m]] : 0.0;
+        double a[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) a[k] = (lane < h && k < w) ? L[off + lane + int64_t(h) * k] : 0.0;
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k < w) {   // uniform
+                const double d = lane_bcast(a[k], k);
+                ok = ok && (d > 0.0) && isfinite(d);
+                const double inv = rsqrt_newton(d);
+                const double l = (lane >= k) ? a[k] * inv : 0.0;   // row k gets sqrt(d)
+                a[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < 32; ++j) a[j] = fma(-l, lane_bcast(l, j), a[j]);
+            }
+        }
+        if (!ok) {
+            if (lane == 0) fail[cand] = b + 1;
+            return;   // uniform: the pivots were broadcast
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k < w && lane < h && lane >= k) L[off + lane + int64_t(h) * k] = a[k];
+        if (lane >= w && lane < h) {
+#pragma unroll
+            for (int k = 0; k < 32; k += 2)
+                *reinterpret_cast<double2 *>(Pr + (lane - w) * 32 + k) =
+                    double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
+        }
+        __syncthreads();
+        auto dot_rows = [&](int pr) {
+            const double2 *x = reinterpret_cast<const double2 *>(Pr + (pr & 0xffff) * 32);
+            const double2 *y = reinterpret_cast<const double2 *>(Pr + (pr >> 16) * 32);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double2 p = x[u], q = y[u];
+                s0 = fma(p.x, q.x, s0);
+                s1 = fma(p.y, q.y, s1);
+            }
+            return s0 + s1;
+        };
+#pragma unroll
+        for (int m = 0; m < kPrefetch; ++m)
+            if (ps[m] >= 0) L[ps[m]] = old[m] - dot_rows(pp[m]);
+        for (int t = 64 * kPrefetch + lane; t < np; t += 64) {
+            const int sl = up_slot[p0 + t];
+            if (sl >= 0) L[sl] -= dot_rows(up_pair[p0 + t]);
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    if (lane == 0) fail[cand] = 0;
+}
+
 __global__ void __launch_bounds__(64)
 k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
        const int64_t *__restrict__ bl_dinv, const double *__restrict__ L, double *__restrict__ Dinv,
@@ -213,65 +297,75 @@ __global__ void __launch_bounds__(256)
 k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
              const int *__restrict__ cl_map, const int *__restrict__ cl_first, const double *__restrict__ Xbar,
              double *__restrict__ Lhat, int *__restrict__ fail) {
-    __shared__ CholLds sh;
+    __shared__ TileLds<64, 64> sh;
     const int r = blockIdx.x;
     const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
     const int ns = cl_first[r + 1] - cl_first[r];
     const int *map = cl_map + cl_map_ptr[r];
-    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
+    const int tid = threadIdx.x;
+    const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
     // packed lower index of clique entry (ii, jj), ii >= jj: jj * (2c - jj + 1) / 2 + (ii - jj)
     auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
-    // Step 2-1: Z = P_r Xbar(C_r, C_r) P_r^T, Z(a, b) = Xbar(C[c-1-a], C[c-1-b])
-    double a[16], m[16];
+    // Step 2-1: Z = P_r Xbar(C_r, C_r) P_r^T, Z(a, b) = Xbar(C[c-1-a], C[c-1-b]);
+    // identity beyond the clique order
+    double a[4][4], m[4][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int k = q + 4 * t;
-        a[t] = (i < c && k <= i) ? Xbar[map[pk(c - 1 - k, c - 1 - i)]] : 0.0;
-        m[t] = (k == i) ? 1.0 : 0.0;
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            a[u][v] = (i < c && k <= i) ? Xbar[map[pk(c - 1 - k, c - 1 - i)]] : (i == k ? 1.0 : 0.0);
+            m[u][v] = (i == k) ? 1.0 : 0.0;
+        }
     // Step 2-2: Z = M_r M_r^T, with M_r^{-1} alongside
     int bad = 0;
-    if (!chol_reg<true>(a, m, c, sh, &bad)) {
+    if (!chol_tile<4, 4, 16, true>(a, m, c, sh, &bad)) {
         if (tid == 0) atomicCAS(fail, 0, r + 1);
         return;
     }
     // Steps 2-3 and 3: L_r = P_r M_r^{-T} P_r^T, i.e. L_r(ii, jj) = M_r^{-1}(c-1-jj, c-1-ii);
-    // its first ns columns are Lhat(C_r, S_r).  This thread holds M_r^{-1}(i, k).
-    if (i < c && i >= c - ns) {
-        const int jj = c - 1 - i;
+    // its first ns columns are Lhat(C_r, S_r), i.e. rows >= c - ns of M_r^{-1}
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int k = q + 4 * t;
-            if (k <= i) Lhat[map[pk(c - 1 - k, jj)]] = m[t];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            if (i < c && i >= c - ns && k <= i) Lhat[map[pk(c - 1 - k, c - 1 - i)]] = m[u][v];
         }
-    }
 }
 
 __global__ void __launch_bounds__(256)
 k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
            const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
            double *__restrict__ alpha_cl) {
-    __shared__ CholLds sh;
+    __shared__ TileLds<64, 64> sh;
     const int r = blockIdx.x;
     const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
     const int *map = cl_map + cl_map_ptr[r];
-    const int tid = threadIdx.x, i = tid >> 2, q = tid & 3;
+    const int tid = threadIdx.x;
+    const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
     auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
-    // the clique block in the reversed order Algorithm 1 factorises in
-    double x[16], dx[16], a[16], unused[16];
+    // the clique block in the reversed order Algorithm 1 factorises in; identity
+    // (and a zero direction) beyond the clique order
+    double x[4][4], dx[4][4], a[4][4], unused[4][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int k = q + 4 * t;
-        const bool in = i < c && k <= i;
-        const int s = in ? map[pk(c - 1 - k, c - 1 - i)] : 0;
-        x[t] = in ? Xbar[s] : 0.0;
-        dx[t] = in ? dX[s] : 0.0;
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            const bool in = i < c && k <= i;
+            const int s = in ? map[pk(c - 1 - k, c - 1 - i)] : 0;
+            x[u][v] = in ? Xbar[s] : (i == k ? 1.0 : 0.0);
+            dx[u][v] = in ? dX[s] : 0.0;
+            unused[u][v] = 0.0;
+        }
     auto test = [&](double al) -> bool {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) a[t] = fma(al, dx[t], x[t]);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[u][v] = fma(al, dx[u][v], x[u][v]);
         int bad = 0;
-        return chol_reg<false>(a, unused, c, sh, &bad);
+        return chol_tile<4, 4, 16, false>(a, unused, c, sh, &bad);
     };
     double res;
     if (test(1.0)) {
@@ -298,10 +392,7 @@ __global__ void k_bracket(int K, int round, const int *__restrict__ fail, double
         if (fail[c] != 0) break;
         best = c;
     }
-    auto cand = [&](int c) {
-        return round == 0 ? pow(10.0, -8.0 * double(K - 1 - c) / double(K - 1))
-                          : bracket[0] + (bracket[1] - bracket[0]) * double(c + 1) / double(K + 1);
-    };
+    auto cand = [&](int c) { return cand_alpha(c, K, round, bracket); };
     if (round == 0) {
         if (best == K - 1) { bracket[0] = 1.0; bracket[1] = 1.0; bracket[2] = 1.0; return; }
         if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 1.0; return; }
@@ -330,7 +421,20 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 
 }  // namespace
 
+int sn_init_grid(int64_t nslot) {
+    int64_t g = (nslot + 255) / 256;
+    return int(g < 1 ? 1 : (g > 256 ? 256 : g));
+}
+
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st) {
+    if (d.max_h <= 64) {
+        hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), 1), dim3(256), 0, st, d.nslot, d.wE, Y,
+                           (const double *)nullptr, (const double *)nullptr, 0, L, int64_t(0));
+        hipLaunchKernelGGL(k_sn_chol_wave, dim3(1), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st, d.nb,
+                           d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
+                           (const double *)nullptr, 0, L, int64_t(0), fail);
+        return;
+    }
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     hipLaunchKernelGGL(k_sn_chol, dim3(1), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
                        d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, (const double *)nullptr,
@@ -341,9 +445,17 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
                       int *fail, double *bracket, hipStream_t st) {
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_sn_chol, dim3(ncand), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
-                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket, r,
-                           cand, d.nslot, fail);
+        if (d.max_h <= 64) {
+            hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), ncand), dim3(256), 0, st, d.nslot, d.wE,
+                               Y, dY, (const double *)bracket, r, cand, d.nslot);
+            hipLaunchKernelGGL(k_sn_chol_wave, dim3(ncand), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st,
+                               d.nb, d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
+                               (const double *)bracket, r, cand, d.nslot, fail);
+        } else {
+            hipLaunchKernelGGL(k_sn_chol, dim3(ncand), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE,
+                               d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY,
+                               (const double *)bracket, r, cand, d.nslot, fail);
+        }
         hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, ncand, r, (const int *)fail, bracket);
     }
 }
