@@ -31,8 +31,8 @@ using namespace sdpc;
 
 namespace {
 
-constexpr int kCand = 256;       // dual step-length candidates per round (one workgroup each)
-constexpr int kDualRounds = 4;   // log grid, then three even refinements: ~4e-9 relative
+constexpr int kCand = 1024;      // dual step-length candidates per round (one wave each, four per CU)
+constexpr int kDualRounds = 2;   // log grid (ratio 1.018), then one even refinement: ~2e-5 relative
 
 struct Timer {
     hipEvent_t a{}, b{};
@@ -59,13 +59,15 @@ struct sdpc_handle {
     double *dX = nullptr, *dY = nullptr, *dz = nullptr;
     double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
-    double *B = nullptr, *g = nullptr, *hcol = nullptr, *pwork = nullptr, *ty = nullptr;
+    double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
     int *flags = nullptr;   // [0..kCand) sn_chol, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2] potrf
     int64_t ldb = 0;
     double last_alpha[2] = {0, 0};
     double scm_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[8]{};
+    int *pflags_f = nullptr, *pflags_b = nullptr;   // hand-over flags of the SCM Cholesky and the SCE solve
+    int epoch = 0;                                    // last epoch used on those flags
     int iters = 0;
 };
 
@@ -500,7 +502,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->dz, size_t(m)));
     TRY(dalloc(h, &h->g, size_t(m)));
     TRY(dalloc(h, &h->hcol, size_t(m)));
-    TRY(dalloc(h, &h->ty, size_t(m)));
     TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->Xh, nn));
@@ -508,7 +509,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->W, nn));
     TRY(dalloc(h, &h->T, std::max<size_t>(size_t(d.nS), 1)));
     TRY(dalloc(h, &h->B, size_t(h->ldb) * std::max(m, 1)));
-    TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
+    TRY(dalloc(h, &h->pflags_f, size_t(potrf_flag_count(m))));
+    TRY(dalloc(h, &h->pflags_b, size_t(potrf_flag_count(m))));
     TRY(dalloc(h, &h->scal, 16));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
@@ -518,6 +520,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flag_count(m) * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
     launch_init_point(d, h->prm.lambda0, h->X, h->Y, h->z, h->st);
     HIPCHK(h, hipGetLastError());
@@ -629,7 +633,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
     HIPCHK(h, hipEventRecord(h->ev[4], st));
-    if (factor) launch_potrf(d.m, B, ldb, h->pwork, h->flags + kCand + 2, st);
+    if (factor) launch_potrf(d.m, B, ldb, h->pflags_f, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(h->ev[5], st));
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(st));
@@ -644,6 +648,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     if (fl[kCand + 1])
         return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[kCand + 1] - 1) + ")");
     if (fl[kCand]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
+    if (factor && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky: an internal hand-over wait ran out");
     if (factor && fl[kCand + 2])
         return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
     return SDPC_OK;
@@ -729,9 +734,9 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipEventRecord(ev[1], st));
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
     launch_set_row(d.m, h->g, h->B + d.m, h->ldb, st);
-    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pflags_f, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[6], st));
-    launch_potrs_bwd(d.m, h->B, h->ldb, h->pwork, h->B + d.m, h->ldb, h->ty, h->dz, st);
+    launch_potrs_bwd(d.m, h->B, h->ldb, h->B + d.m, h->ldb, h->dz, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[2], st));
     // dY = G - sum dz_k A_k ; dX on E
     launch_assemble(d, h->dz, 0.0, 1.0, h->G, h->dY, st);
@@ -743,8 +748,9 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     double ap = 0.0;
     HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
-    if (read_flag(h, kCand + 2))
-        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite");
+    const int pf = read_flag(h, kCand + 2);
+    if (pf < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
+    if (pf) return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite");
     float ms_rhs = 0, ms_chol = 0, ms_pm = 0, ms_potrf = 0;
     (void)hipEventElapsedTime(&ms_potrf, ev[1], ev[6]);
     (void)hipEventElapsedTime(&ms_rhs, ev[0], ev[1]);
@@ -842,10 +848,11 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m) {
     if (!h || !d_B || m < 0 || ldb < m || m > h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_potrf arguments") : SDPC_E_ARG;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), h->st));
-    launch_potrf(m, d_B, ldb, h->pwork, h->flags + kCand + 2, h->st);
+    launch_potrf(m, d_B, ldb, h->pflags_f, ++h->epoch, h->flags + kCand + 2, h->st);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(h->st));
     const int f = read_flag(h, kCand + 2);
+    if (f < 0) return fail(h, SDPC_E_HIP, "internal hand-over wait ran out");
     if (f) return fail(h, SDPC_E_NOT_PD, "matrix not positive definite at pivot " + std::to_string(f - 1));
     return SDPC_OK;
 }

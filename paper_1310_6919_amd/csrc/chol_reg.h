@@ -33,6 +33,14 @@ __device__ inline double rsqrt_newton(double d) {
     return y;
 }
 
+// The value of x held by lane `lane` of the wave (a uniform lane index), through
+// two readlanes into scalar registers.
+__device__ inline double lane_bcast(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
 template <int NR, int NC>
 struct TileLds {
     double col[2][NR];   // column k of the working matrix (unscaled), rows 0..NR-1

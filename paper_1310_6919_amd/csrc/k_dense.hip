@@ -1,21 +1,26 @@
 // Dense FP64 Cholesky of the Schur complement matrix, B = R R^T (type (i) of
-// Section 3.1), and the two triangular solves of the SCE (eq. SCE).
+// Section 3.1), and the backward substitution of the SCE (eq. SCE).
 //
-// Right-looking blocked algorithm with 64-wide block columns:
-//   k_potrf_diag   one workgroup factorises the 64 x 64 diagonal block in LDS
-//                  and forms the inverse of its factor at the same time
-//                  (forward elimination against the identity, one column per
-//                  pivot step);
-//   k_trsm_panel   R(I, J) = B(I, J) R(J, J)^{-T} for every 64-row tile below,
-//                  as a product with the explicit inverse;
-//   k_syrk_tiles   B(I, K) -= R(I, J) R(K, J)^T for every lower tile pair of the
-//                  trailing matrix.
-// Rows beyond m can ride along: with the right-hand side g stored as row m,
-// the same sweep leaves R^{-1} g in that row (the forward substitution of the
-// SCE for free), and only the backward substitution R^T x = R^{-1} g remains.
-// Both products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64): each
-// of the four waves of a workgroup owns a 32 x 32 quadrant of the 64 x 64
-// output tile, i.e. 2 x 2 MFMA blocks of 16 x 16.
+// Right-looking, 64-wide column blocks, one fused launch per block column s:
+//   workgroup 0          applies the pending panel s-1 to the diagonal tile and
+//                        factorises it in one wave (lane = row, pivot column
+//                        broadcast with readlane), then releases flags[s];
+//   workgroups 1..nt-1   apply panel s-1 to their tile of column block s, wait
+//                        for flags[s] and solve X R_ss^T = C by forward
+//                        substitution (lane = row of the tile);
+//   the others           apply panel s-1 to every lower tile of the column blocks
+//                        s+1 .. (the bulk of the trailing update), overlapping the
+//                        diagonal factorisation of the same launch.
+// So column block s+1 only lacks panel s when launch s+1 starts, and the launch
+// boundary is the only grid-wide synchronisation.  Rows beyond m ride along:
+// with the right-hand side g stored as row m, the sweep leaves R^{-1} g there
+// (the forward substitution of the SCE), and only R^T x = R^{-1} g remains,
+// done by one launch whose workgroups hand the blocks of x down through flags.
+//
+// Every wait is a bounded spin on a flag released by a workgroup with a lower
+// index (dispatched earlier), so it cannot deadlock; a wait that runs out marks
+// the call failed (fail = -1) instead of hanging.  Flags hold the epoch of the
+// call that released them, so they never need to be cleared.
 #include "chol_reg.h"
 #include "kernels.h"
 
@@ -24,233 +29,397 @@ namespace sdpc {
 namespace {
 
 constexpr int NB = 64;
-constexpr int LDT = NB + 1;   // padded LDS row length
+constexpr int LDS_LD = NB + 1;          // padded row length of a tile in LDS
+constexpr int kSpinLimit = 1 << 20;     // about a second of polling before a wait gives up
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// C(64x64) = A(64xK) * Bm(64xK)^T from LDS (row-major, ld LDT), K <= 64.
-// Result returned per wave as acc[2][2] (16x16 blocks of its 32x32 quadrant).
-// Operand layout of the FP64 16x16x4 MFMA: lane l supplies A(l % 16, l / 16)
-// and B(l / 16, l % 16); element r of lane l's result is D(4 r + l / 16, l % 16)
-// (checked on gfx950 with a lane-layout probe).
-// Here: lane l, element r holds C(qr + 16 ti + 4 r + l / 16, qc + 16 tj + l % 16).
-__device__ inline void tile_gemm_nt(const double *A, const double *Bm, int K, d4 acc[2][2]) {
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int qr = 32 * (w % 2), qc = 32 * (w / 2);
-    const int li = lane % 16, lk = lane / 16;
-    for (int ti = 0; ti < 2; ++ti)
-        for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < K; k += 4) {
-        double a[2], b[2];
-        for (int t = 0; t < 2; ++t) {
-            a[t] = A[(qr + 16 * t + li) * LDT + k + lk];
-            b[t] = Bm[(qc + 16 * t + li) * LDT + k + lk];
+// One 64 x 64 output tile of C = A B^T (A, B column-major in global memory),
+// operands loaded straight into registers in the FP64 16x16x4 MFMA layout.
+// Operand layout of the MFMA D = X Z: lane l supplies X(l % 16, l / 16) and
+// Z(l / 16, l % 16); element r of lane l's result is D(4 r + l / 16, l % 16)
+// (checked on gfx950 with a lane-layout probe).  The product is formed as
+// C^T = B A^T, so lane l, element r of acc[ti][tj] holds
+//   C(qr + 16 ti + l % 16, qc + 16 tj + 4 r + l / 16),
+// sixteen consecutive rows of one column per group of 16 lanes: operand loads
+// and the write-back of a column-major C move whole 128-byte lines.  Each wave
+// owns a 32 x 32 quadrant (qr, qc); all its operand loads are issued before the
+// first product so one memory latency covers the whole tile.
+struct TileIdx {
+    int lane, li, lk, qr, qc;
+    __device__ TileIdx() {
+        lane = threadIdx.x % 64;
+        const int w = threadIdx.x / 64;
+        li = lane % 16;
+        lk = lane / 16;
+        qr = 32 * (w % 2);
+        qc = 32 * (w / 2);
+    }
+    __device__ int row(int ti) const { return qr + 16 * ti + li; }                 // tile row of acc[ti][.]
+    __device__ int col(int tj, int r) const { return qc + 16 * tj + 4 * r + lk; }   // tile column of element r
+};
+
+// acc += A(ar0 + [0,64), ac0 + [0,kk)) * B(br0 + [0,64), bc0 + [0,kk))^T; rows of A at or
+// beyond amax and rows of B at or beyond bmax read as zero; kk <= 64.
+__device__ inline void tile_mma(const TileIdx &t, const double *A, int64_t lda, int ar0, int amax, int ac0,
+                                const double *Bm, int64_t ldbm, int br0, int bmax, int bc0, int kk, d4 acc[2][2]) {
+    double a[2][16], b[2][16];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+        const int k = 4 * ks + t.lk;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ra = ar0 + t.qr + 16 * u + t.li, rb = br0 + t.qc + 16 * u + t.li;
+            a[u][ks] = (k < kk && ra < amax) ? A[ra + lda * (ac0 + k)] : 0.0;
+            b[u][ks] = (k < kk && rb < bmax) ? Bm[rb + ldbm * (bc0 + k)] : 0.0;
         }
+    }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
         for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
             for (int tj = 0; tj < 2; ++tj)
-                acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+                acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[tj][ks], a[ti][ks], acc[ti][tj], 0, 0, 0);
+}
+
+__device__ inline void zero_acc(d4 acc[2][2]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Bounded wait for *flag == epoch (one thread); false if the wait ran out.
+__device__ inline bool flag_wait(const int *flag, int epoch) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+__device__ inline void flag_release(int *flag, int epoch) {
+    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Right-looking elimination of 32 columns held one row per lane (a[k] = A(lane,
+// C0 + k)); pivot k sits in lane C0 + k and reaches the other lanes, with the
+// scaled column, through readlane: no LDS, no barrier.  Lanes above the pivot get
+// zero multipliers.  A pivot that is not positive and finite leaves a NaN on the
+// diagonal of L (1/sqrt of it is NaN or makes 0 * inf), so the caller checks the
+// diagonal afterwards instead of testing every pivot inside the chain.
+template <int C0>
+__device__ inline void panel32_wave(double (&a)[32]) {
+    const int lane = threadIdx.x % 64;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const double d = lane_bcast(a[k], C0 + k);
+        const double inv = rsqrt_newton(d);
+        const double l = (lane >= C0 + k) ? a[k] * inv : 0.0;   // row C0 + k gets sqrt(d)
+        a[k] = l;
+#pragma unroll
+        for (int j = k + 1; j < 32; ++j) a[j] = fma(-l, lane_bcast(l, C0 + j), a[j]);
     }
 }
 
-// load rows [r0, r0+64) x columns [c0, c0+kk) of a column-major matrix into LDS row-major,
-// zero outside [0, rmax) rows and beyond kk columns (up to 64)
-__device__ inline void load_tile(double *S, const double *M, int64_t ld, int r0, int rmax, int c0, int kk) {
-    // 16 loads per thread in flight before the LDS stores (256 threads x 16 = 64 x 64)
-    double v[16];
-    const int i = threadIdx.x % NB, k0 = threadIdx.x / NB;   // consecutive threads -> consecutive rows
-    const int r = r0 + i;
+// Cholesky of a 64 x 64 matrix held one row per lane by one wave, in two 32-column
+// panels: lo[k] = A(lane, k), hi[k] = A(lane, 32 + k) (lower part used; the upper
+// part ends meaningless).  Between the panels, A22 -= L21 L21^T is one 32 x 32 x 32
+// product on the FP64 MFMA through the LDS scratch W (at least 32 x 33 + 32 x 33
+// doubles).
+__device__ inline void potrf64_wave(double (&lo)[32], double (&hi)[32], double *W) {
+    const int lane = threadIdx.x % 64;
+    panel32_wave<0>(lo);
+    constexpr int LW = 33;
+    double *D = W + 32 * LW;
+    if (lane >= 32) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int k = k0 + 4 * u;
-        v[u] = (r < rmax && k < kk) ? M[r + ld * (c0 + k)] : 0.0;
+        for (int k = 0; k < 32; ++k) W[(lane - 32) * LW + k] = lo[k];   // W = L21, row-major
     }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's own LDS stores are done
+    // D = W W^T, lower 16 x 16 blocks (0,0), (1,0), (1,1); lane l supplies
+    // X(l % 16, l / 16) and Z(l / 16, l % 16); result element r: D(4 r + l / 16, l % 16)
+    const int li = lane % 16, lk = lane / 16;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) S[i * LDT + k0 + 4 * u] = v[u];
+    for (int blk = 0; blk < 3; ++blk) {
+        const int bi = (blk == 0) ? 0 : 1, bj = (blk == 2) ? 1 : 0;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const double x = W[(16 * bi + li) * LW + 4 * ks + lk];
+            const double z = W[(16 * bj + li) * LW + 4 * ks + lk];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, z, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) D[(16 * bi + 4 * r + lk) * LW + 16 * bj + li] = acc[r];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    if (lane >= 32) {
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k <= lane - 32) hi[k] -= D[(lane - 32) * LW + k];
+    }
+    panel32_wave<32>(hi);
 }
 
 __global__ void __launch_bounds__(256)
-k_potrf_diag(double *__restrict__ B, int64_t ldb, int j, int jb, double *__restrict__ Linv, int *__restrict__ fail) {
-    __shared__ TileLds<64, 64> sh;
+k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__restrict__ flags, int epoch,
+            int *__restrict__ fail) {
+    __shared__ double S[NB * LDS_LD];   // the updated tile, row-major; later the diagonal factor, column-major
+    __shared__ double invd[NB];
+    __shared__ int go;
     const int tid = threadIdx.x;
-    const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
-    double a[4][4], r[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + u, k = j0 + v;
-            a[u][v] = (i < jb && k <= i) ? B[(j + i) + ldb * (j + k)] : (i == k ? 1.0 : 0.0);
-            r[u][v] = (i == k) ? 1.0 : 0.0;
+    const TileIdx t;
+    const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
+    const int nt = T_rows - s;
+    const int J0 = NB * s;
+    const int jb = (m - J0 < NB) ? (m - J0) : NB;
+    if (int(blockIdx.x) >= nt) {
+        // bulk: panel s-1 applied to the lower tile (I, K), s+1 <= K <= I
+        int q = int(blockIdx.x) - nt, K = s + 1;
+        while (K < T_cols && q >= T_rows - K) {
+            q -= T_rows - K;
+            ++K;
         }
-    int bad = 0;
-    if (!chol_tile<4, 4, 16, true>(a, r, jb, sh, &bad)) {
-        if (tid == 0) atomicCAS(fail, 0, j + bad + 1);
+        if (K >= T_cols) return;
+        const int I = K + q;
+        const int I0 = NB * I, K0 = NB * K, P0 = J0 - NB;
+        double c[2][2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = I0 + t.row(a), gk = K0 + t.col(b, r);
+                    c[a][b][r] = (gi < rows && gk < m && gi >= gk) ? B[gi + ldb * gk] : 0.0;
+                }
+        d4 acc[2][2];
+        zero_acc(acc);
+        tile_mma(t, B, ldb, I0, rows, P0, B, ldb, K0, m, P0, NB, acc);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = I0 + t.row(a), gk = K0 + t.col(b, r);
+                    if (gi < rows && gk < m && gi >= gk) B[gi + ldb * gk] = c[a][b][r] - acc[a][b][r];
+                }
         return;
     }
-    // the factor back into the lower part of the block, its inverse into Linv
-    // (column-major 64 x 64, zero beyond the block)
+    // column block s: tile row I, with panel s-1 applied
+    const int I = s + int(blockIdx.x), I0 = NB * I;
+    const bool diag = (I == s);
+    {
+        double c[2][2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + u, k = j0 + v;
-            if (i < jb && k <= i) B[(j + i) + ldb * (j + k)] = a[u][v];
-            Linv[i + NB * k] = (i < jb && k < jb) ? r[u][v] : 0.0;
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = I0 + t.row(a), gk = t.col(b, r);
+                    c[a][b][r] = (gi < rows && gk < jb && (!diag || gi >= J0 + gk)) ? B[gi + ldb * (J0 + gk)] : 0.0;
+                }
+        if (s >= 1) {
+            d4 acc[2][2];
+            zero_acc(acc);
+            tile_mma(t, B, ldb, I0, rows, J0 - NB, B, ldb, J0, m, J0 - NB, NB, acc);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) c[a][b][r] -= acc[a][b][r];
         }
-}
-
-__global__ void __launch_bounds__(256)
-k_trsm_panel(double *__restrict__ B, int64_t ldb, int m, int j, int jb, const double *__restrict__ Linv) {
-    // m here is the number of rows (the order of B, plus riding rows)
-    __shared__ double A[NB * LDT];
-    __shared__ double Bm[NB * LDT];
-    const int r0 = j + jb + blockIdx.x * NB;
-    load_tile(A, B, ldb, r0, m, j, jb);
-    load_tile(Bm, Linv, NB, 0, NB, 0, NB);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S[t.row(a) * LDS_LD + t.col(b, r)] = c[a][b][r];
+    }
     __syncthreads();
-    d4 acc[2][2];
-    tile_gemm_nt(A, Bm, jb, acc);
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int qr = 32 * (w % 2), qc = 32 * (w / 2);
-    for (int ti = 0; ti < 2; ++ti)
-        for (int tj = 0; tj < 2; ++tj)
-            for (int r = 0; r < 4; ++r) {
-                const int i = qr + 16 * ti + 4 * r + lane / 16;
-                const int k = qc + 16 * tj + lane % 16;
-                if (r0 + i < m && k < jb) B[(r0 + i) + ldb * (j + k)] = acc[ti][tj][r];
+    if (diag) {
+        if (tid < 64) {
+            // rows of the tile below the block's own jb rows (right-hand-side rows riding
+            // along the last block) keep their values in the jb active columns: the
+            // elimination then performs their forward substitution
+            const int lane = tid;
+            const bool real = J0 + lane < rows;
+            double lo[32], hi[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const int k2 = 32 + k;
+                lo[k] = (real && k < jb) ? (k <= lane ? S[lane * LDS_LD + k] : 0.0) : (lane == k ? 1.0 : 0.0);
+                hi[k] = (real && k2 < jb) ? (k2 <= lane ? S[lane * LDS_LD + k2] : 0.0) : (lane == k2 ? 1.0 : 0.0);
             }
-}
-
-__global__ void __launch_bounds__(256)
-k_syrk_tiles(double *__restrict__ B, int64_t ldb, int rows, int m, int j, int jb) {
-    __shared__ double A[NB * LDT];
-    __shared__ double Bm[NB * LDT];
-    const int ti = blockIdx.x, tk = blockIdx.y;
-    if (tk > ti) return;
-    const int base = j + jb;
-    const int I0 = base + ti * NB, K0 = base + tk * NB;
-    load_tile(A, B, ldb, I0, rows, j, jb);
-    load_tile(Bm, B, ldb, K0, m, j, jb);
-    __syncthreads();
-    d4 acc[2][2];
-    tile_gemm_nt(A, Bm, jb, acc);
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int qr = 32 * (w % 2), qc = 32 * (w / 2);
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c)
-            for (int r = 0; r < 4; ++r) {
-                const int gi = I0 + qr + 16 * a + 4 * r + lane / 16;
-                const int gk = K0 + qc + 16 * c + lane % 16;
-                if (gi < rows && gk < m && gi >= gk) B[gi + ldb * gk] -= acc[a][c][r];
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile is in registers before S is reused
+            potrf64_wave(lo, hi, S);   // S is free again: the tile is in registers
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                S[lane * LDS_LD + k] = lo[k];
+                S[lane * LDS_LD + 32 + k] = hi[k];
             }
-}
-
-// backward step of R^T x = y over block J: x_J = Linv_J^T y_J, then
-// y_c -= R(J, c)^T x_J for every column c before J (one wave per column)
-__global__ void __launch_bounds__(256)
-k_trsv_bwd_wave(const double *__restrict__ R, int64_t ldb, int j, int jb, const double *__restrict__ Linv,
-                double *__restrict__ y, double *__restrict__ x) {
-    __shared__ double xs[NB];
-    const int tid = threadIdx.x;
-    if (tid < jb) {
-        double s = 0.0;
-        for (int k = tid; k < jb; ++k) s += Linv[k + NB * tid] * y[j + k];
-        xs[tid] = s;
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            // every pivot of the block must have been positive and finite
+            const double dg = S[lane * LDS_LD + lane];
+            const unsigned long long badm = __ballot(lane < jb && !((dg > 0.0) && isfinite(dg)));
+            if (badm != 0ull && lane == 0) atomicCAS(fail, 0, J0 + __ffsll((long long)badm));
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NB * NB; idx += blockDim.x) {   // the factor back into B, lower part
+            const int i = idx % NB, k = idx / NB;
+            if (J0 + i < rows && k < jb && k <= i) B[(J0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
+        }
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) flag_release(&flags[s], epoch);
+        return;
+    }
+    // panel tile: wait for the diagonal factor of this launch
+    if (tid == 0) {
+        const bool ok = flag_wait(&flags[s], epoch);
+        if (!ok) atomicCAS(fail, 0, -1);
+        go = ok && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     }
     __syncthreads();
-    if (blockIdx.x == 0 && tid < jb) x[j + tid] = xs[tid];
-    const int lane = tid % 64;
-    const double xl = lane < jb ? xs[lane] : 0.0;
-    for (int c = blockIdx.x * 4 + tid / 64; c < j; c += gridDim.x * 4) {
-        double v = lane < jb ? R[(j + lane) + ldb * c] * xl : 0.0;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) y[c] -= v;
-    }
-}
-
-// forward step: x_J = Linv_J y_J ; y_i -= R(i, J) x_J for i beyond J
-__global__ void __launch_bounds__(256)
-k_trsv_fwd(const double *__restrict__ R, int64_t ldb, int m, int j, int jb, const double *__restrict__ Linv,
-           double *__restrict__ y, double *__restrict__ x) {
-    __shared__ double xs[NB];
-    const int tid = threadIdx.x;
-    if (tid < jb) {
-        double s = 0.0;
-        for (int k = 0; k <= tid; ++k) s += Linv[tid + NB * k] * y[j + k];
-        xs[tid] = s;
+    if (!go) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double cr[64];   // wave 0: row tid of the tile
+    if (tid < 64) {
+#pragma unroll
+        for (int k = 0; k < 64; ++k) cr[k] = S[tid * LDS_LD + k];
     }
     __syncthreads();
-    if (blockIdx.x == 0 && tid < jb) x[j + tid] = xs[tid];
-    for (int i = j + jb + blockIdx.x * blockDim.x + tid; i < m; i += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int k = 0; k < jb; ++k) s += R[i + ldb * (j + k)] * xs[k];
-        y[i] -= s;
+    // the diagonal factor, column-major, identity beyond jb
+    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+        const int j = idx % NB, k = idx / NB;
+        S[k * NB + j] = (j < jb && k < jb) ? (j >= k ? B[(J0 + j) + ldb * (J0 + k)] : 0.0) : (j == k ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    if (tid < NB) invd[tid] = 1.0 / S[tid * NB + tid];
+    __syncthreads();
+    if (tid < 64) {
+        // X R_ss^T = C: x_k = (c_k - sum_{j<k} x_j R(k, j)) / R(k, k), right-looking
+#pragma unroll
+        for (int k = 0; k < 64; ++k) {
+            const double x = cr[k] * invd[k];
+            cr[k] = x;
+#pragma unroll
+            for (int j = k + 1; j < 64; ++j) {
+                cr[j] = fma(-x, S[k * NB + j], cr[j]);
+                if ((j - k) % 16 == 0) __builtin_amdgcn_sched_barrier(0);   // at most 16 operands in flight
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // every read of the factor has returned
+#pragma unroll
+        for (int k = 0; k < 64; ++k) S[tid * LDS_LD + k] = cr[k];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {   // the solved tile back into B
+        const int i = idx % NB, k = idx / NB;
+        if (I0 + i < rows && k < jb) B[(I0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
     }
 }
 
-__global__ void k_copy(int m, const double *__restrict__ a, double *__restrict__ b) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) b[i] = a[i];
+// R^T x = u, R lower (the factor left in B), u read with a stride (row m of B).
+// Workgroup q handles block J = T-1-q: it accumulates R(K, J)^T x_K for K > J as
+// the blocks x_K are released, then solves with R_JJ^T by backward substitution
+// (one wave, lane = row) and releases x_J.
+__global__ void __launch_bounds__(256)
+k_trsv_bwd_chain(const double *__restrict__ R, int64_t ldb, int m, const double *__restrict__ u, int64_t ustride,
+                 double *__restrict__ x, int *__restrict__ flags, int epoch, int *__restrict__ fail) {
+    __shared__ double D[NB * LDS_LD];   // R_JJ, row-major
+    __shared__ double part[4][NB];
+    __shared__ double xk[NB];
+    __shared__ int go;
+    const int tid = threadIdx.x;
+    const int T = (m + NB - 1) / NB;
+    const int J = T - 1 - int(blockIdx.x);
+    const int J0 = NB * J;
+    const int jb = (m - J0 < NB) ? (m - J0) : NB;
+    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+        const int i = idx % NB, j = idx / NB;   // consecutive threads: consecutive rows of column j
+        D[i * LDS_LD + j] = (i < jb && j <= i) ? R[(J0 + i) + ldb * (J0 + j)] : 0.0;
+    }
+    const int jj = tid % NB, pg = tid / NB;   // column jj of the block, rows pg*16 .. pg*16+15 of tile K
+    double acc = 0.0;
+    for (int K = T - 1; K > J; --K) {
+        const int K0 = NB * K;
+        const int kb = (m - K0 < NB) ? (m - K0) : NB;
+        double rv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = pg * 16 + i;
+            rv[i] = (r < kb && jj < jb) ? R[(K0 + r) + ldb * (J0 + jj)] : 0.0;
+        }
+        if (tid == 0) {
+            const bool ok = flag_wait(&flags[K], epoch);
+            if (!ok) atomicCAS(fail, 0, -1);
+            go = ok;
+        }
+        __syncthreads();
+        if (!go) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (tid < NB) xk[tid] = (tid < kb) ? x[K0 + tid] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc = fma(rv[i], xk[pg * 16 + i], acc);
+        __syncthreads();
+    }
+    part[pg][jj] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        const int lane = tid;
+        double v = (lane < jb) ? u[(J0 + lane) * ustride] : 0.0;
+        v -= part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        // R_JJ^T x_J = v, from the last row up: x_i = v_i / R(i, i), then
+        // v_j -= R(i, j) x_i for j < i
+        const double dii = (lane < jb) ? D[lane * LDS_LD + lane] : 1.0;
+#pragma unroll
+        for (int i = 63; i >= 0; --i) {
+            const double xi = lane_bcast(v / dii, i);
+            if (lane == i) v = xi;
+            else if (lane < i) v = fma(-D[i * LDS_LD + lane], xi, v);
+        }
+        if (lane < jb) x[J0 + lane] = v;
+        __threadfence();
+        if (lane == 0) flag_release(&flags[J], epoch);
+    }
 }
 
 __global__ void k_scatter_strided(int m, const double *__restrict__ a, double *__restrict__ b, int64_t stride) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) b[i * stride] = a[i];
 }
 
-__global__ void k_copy_strided(int m, const double *__restrict__ a, int64_t stride, double *__restrict__ b) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) b[i] = a[i * stride];
-}
-
 }  // namespace
 
-size_t potrf_work_doubles(int m) { return size_t((m + NB - 1) / NB) * NB * NB; }
+int potrf_flag_count(int m) { return (m + NB - 1) / NB + 1; }
 
-void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *fail, hipStream_t st) {
-    for (int j = 0, s = 0; j < m; j += NB, ++s) {
-        const int jb = (m - j < NB) ? (m - j) : NB;
-        double *Linv = work + size_t(s) * NB * NB;
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, B, ldb, j, jb, Linv, fail);
-        const int rest_rows = rows - j - jb;
-        if (rest_rows <= 0) break;
-        const int nt_r = (rest_rows + NB - 1) / NB;
-        hipLaunchKernelGGL(k_trsm_panel, dim3(nt_r), dim3(256), 0, st, B, ldb, rows, j, jb, Linv);
-        const int rest_cols = m - j - jb;
-        if (rest_cols <= 0) continue;
-        const int nt_c = (rest_cols + NB - 1) / NB;
-        hipLaunchKernelGGL(k_syrk_tiles, dim3(nt_r, nt_c), dim3(256), 0, st, B, ldb, rows, m, j, jb);
+void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, int *flags, int epoch, int *fail, hipStream_t st) {
+    const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
+    for (int s = 0; s < T_cols; ++s) {
+        const int nt = T_rows - s;
+        int nbulk = 0;
+        if (s >= 1)
+            for (int K = s + 1; K < T_cols; ++K) nbulk += T_rows - K;
+        hipLaunchKernelGGL(k_chol_step, dim3(nt + nbulk), dim3(256), 0, st, B, ldb, m, rows, s, flags, epoch, fail);
     }
 }
 
-void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st) {
-    launch_potrf_rows(m, m, B, ldb, work, fail, st);
+void launch_potrf(int m, double *B, int64_t ldb, int *flags, int epoch, int *fail, hipStream_t st) {
+    launch_potrf_rows(m, m, B, ldb, flags, epoch, fail, st);
 }
 
-void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *dinv, const double *u, int64_t ustride,
-                      double *y, double *x, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy_strided, dim3((m + 255) / 256), dim3(256), 0, st, m, u, ustride, y);
-    const int nsteps = (m + NB - 1) / NB;
-    for (int s = nsteps - 1; s >= 0; --s) {
-        const int j = s * NB;
-        const int jb = (m - j < NB) ? (m - j) : NB;
-        int grid = (j + 3) / 4;
-        if (grid < 1) grid = 1;
-        if (grid > 1024) grid = 1024;
-        hipLaunchKernelGGL(k_trsv_bwd_wave, dim3(grid), dim3(256), 0, st, R, ldb, j, jb,
-                           dinv + size_t(s) * NB * NB, y, x);
-    }
-}
-
-void launch_potrs(int m, const double *R, int64_t ldb, const double *dinv, const double *g, double *y, double *x,
-                  hipStream_t st) {
-    // forward: R u = g  (u into x), with y as the running right-hand side
-    hipLaunchKernelGGL(k_copy, dim3((m + 255) / 256), dim3(256), 0, st, m, g, y);
-    for (int j = 0, s = 0; j < m; j += NB, ++s) {
-        const int jb = (m - j < NB) ? (m - j) : NB;
-        const int rest = m - j - jb;
-        const int grid = rest > 0 ? (rest + 255) / 256 : 1;
-        hipLaunchKernelGGL(k_trsv_fwd, dim3(grid < 256 ? grid : 256), dim3(256), 0, st, R, ldb, m, j, jb,
-                           dinv + size_t(s) * NB * NB, y, x);
-    }
-    launch_potrs_bwd(m, R, ldb, dinv, x, 1, y, x, st);
+void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *u, int64_t ustride, double *x, int *flags,
+                      int epoch, int *fail, hipStream_t st) {
+    const int T = (m + NB - 1) / NB;
+    if (T > 0)
+        hipLaunchKernelGGL(k_trsv_bwd_chain, dim3(T), dim3(256), 0, st, R, ldb, m, u, ustride, x, flags, epoch, fail);
 }
 
 void launch_set_row(int m, const double *g, double *row, int64_t stride, hipStream_t st) {

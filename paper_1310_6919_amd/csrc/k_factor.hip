@@ -160,12 +160,6 @@ k_cand_init(int64_t nslot, const double *__restrict__ wE, const double *__restri
         L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? fma(al, dY[s], Y[s]) : Y[s]);
 }
 
-__device__ inline double lane_bcast(double x, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
-
 // Y = N N^T on the storage blocks by a single wave (panels of at most 64 rows and
 // 32 columns).  Lane i holds row i of the panel in registers; the pivot and the
 // scaled pivot column reach the other lanes through readlane, so the elimination
