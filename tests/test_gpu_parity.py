@@ -277,3 +277,75 @@ def test_solve_normmin_sigma_max():
     smax = np.linalg.svd(Fy, compute_uv=False)[0]
     assert abs(z[0] - smax) <= 1e-7 * smax
     h.close()
+
+
+# ----------------------------------------------------------------- full sizes
+# The bench workload (max-cut on a band graph, n = m = 4000, bandwidth 20) and the
+# norm-minimisation SDP (n = 2010, m = 64) at their real sizes, in the launch
+# configuration the bench uses (default parameters).
+
+
+def test_scm_central_point_full_size():
+    """X = mu Y^{-1} on E at n = m = 4000: then X^ = mu Y^{-1} and, for max-cut,
+    B = mu (Y^{-1} o Y^{-1}) entry by entry (the whole lower triangle)."""
+    prob = sdpgen.maxcut_band(4000, 20, 0.5, 0)
+    rng = np.random.default_rng(21)
+    rows, cols = aggregate_pattern(prob)
+    Y = sdpgen.random_pd_on_pattern(prob.n, rows, cols, rng)
+    mu = 0.05
+    Yi = np.linalg.inv(Y)
+    h = _create(prob)
+    B = h.sdpc_scm(dev(to_E(h, mu * Yi)), dev(to_E(h, Y)), factor=True)
+    Bl = np.tril(host(B))
+    ref = np.tril(mu * Yi * Yi)
+    # with factor=True the lower triangle holds R; rebuild B = R R^T on a sample of rows
+    sel = np.sort(rng.choice(prob.n, 64, replace=False))
+    Rs = Bl[sel]
+    Bs = Rs @ Bl.T
+    full_ref = mu * Yi * Yi
+    assert rel_err(Bs, full_ref[sel]) <= 1e-10
+    h.close()
+    h = _create(prob)
+    B = h.sdpc_scm(dev(to_E(h, mu * Yi)), dev(to_E(h, Y)))
+    assert rel_err(np.tril(host(B)), ref) <= 1e-10
+    h.close()
+
+
+def test_solve_bench_workload_matches_golden():
+    """Objective at gap 1e-7 (the bench's stopping rule) within 1e-7 of the dense
+    oracle's optimum, and z at gap 1e-9 within 1e-6 of the oracle's z (both from
+    tests/golden/oracle_cfg2.json, written by tests/golden/make_golden.py)."""
+    prob = sdpgen.maxcut_band(4000, 20, 0.5, 0)
+    g = golden("cfg2")
+    ref_obj = (g["pobj"] + g["dobj"]) / 2
+    h = _create(prob)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    obj = (r["pobj"] + r["dobj"]) / 2
+    assert abs(obj - ref_obj) <= 1e-7 * max(1.0, abs(ref_obj))
+    assert r["rel_gap"] <= 1e-7 and r["pinf"] <= 1e-7 and r["dinf"] <= 1e-7
+    h.close()
+    h = _create(prob, gap_tol=1e-9, feas_tol=1e-9)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    _, _, z = h.sdpc_get_solution()
+    gz = np.asarray(g["z"])
+    assert np.abs(host(z) - gz).max() <= 1e-6 * max(1.0, np.abs(gz).max())
+    h.close()
+
+
+def test_solve_normmin_full_size_matches_golden():
+    """Norm minimisation, p = 2000, q = 10, 63 coefficients (n = 2010, m = 64):
+    objective within 1e-7 and z within 1e-6 of the dense oracle at gap 1e-10."""
+    prob = sdpgen.normmin(2000, 10, 63, 0)
+    g = golden("cfg3")
+    ref_obj = (g["pobj"] + g["dobj"]) / 2
+    h = _create(prob, gap_tol=1e-9, feas_tol=1e-9)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    obj = (r["pobj"] + r["dobj"]) / 2
+    assert abs(obj - ref_obj) <= 1e-7 * max(1.0, abs(ref_obj))
+    _, _, z = h.sdpc_get_solution()
+    gz = np.asarray(g["z"])
+    assert np.abs(host(z) - gz).max() <= 1e-6 * max(1.0, np.abs(gz).max())
+    h.close()
