@@ -36,6 +36,15 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1310_6919_amd", "csrc", "k_dense.hip")
+
+
+def source_sha1(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -84,7 +93,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "potrf_traffic.json"),
-                    help="HBM traffic per launch from rocprofv3 counters (json), if present")
+                    help="HBM traffic per factorisation from rocprofv3 counters (json), if present")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy kernel of known size, "
+                         "to scale FETCH_SIZE / WRITE_SIZE counters taken on the same command)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -97,6 +109,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     prob = workload()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -128,8 +149,11 @@ def main():
     achieved = flops / (potrf_ms * 1e-3) / 1e12
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
+        # counters count only for the kernel source they were taken on
         try:
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+            rec = json.load(open(args.traffic))
+            if rec.get("source_sha1") == source_sha1(KERNEL_SOURCE):
+                traffic = rec.get("bytes_per_factorisation")
         except Exception:
             traffic = None
     out = {
@@ -157,7 +181,8 @@ def main():
             "pmatrix_and_steps": statistics.median([r["t_pmatrix_ms"] / r["iters"] for r in results]),
         },
         "roofline": {
-            "kernel": "SCM Cholesky (dense FP64, MFMA)",
+            "kernel": "SCM Cholesky: k_chol_step, one launch per 64-column block (%d per factorisation)"
+                      % ((m + 63) // 64),
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
