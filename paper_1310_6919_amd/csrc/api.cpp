@@ -219,6 +219,10 @@ static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::v
     h->d.nbwd = h->slots.nbwd;
     h->d.max_h = S.max_h;
     h->d.max_w = S.max_w;
+    h->d.max_panel = 0;
+    for (int b = 0; b < S.nb; ++b)
+        h->d.max_panel = std::max<int64_t>(h->d.max_panel, (S.bl_rptr[b + 1] - S.bl_rptr[b]) *
+                                                                int64_t(S.bl_first[b + 1] - S.bl_first[b]));
     if (solve_tile_width(h->d) == 0)
         return fail(h, SDPC_E_PATTERN, "substitution frontier too wide for LDS (" + std::to_string(h->d.nfwd) + "+" +
                                            std::to_string(h->d.nbwd) + " live rows)");
@@ -245,9 +249,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     d.max_h = S.max_h;
     d.max_w = S.max_w;
     d.max_clique = S.max_clique;
-    for (int b = 0; b < S.nb; ++b)
-        d.max_panel = std::max<int64_t>(d.max_panel, (S.bl_rptr[b + 1] - S.bl_rptr[b]) *
-                                                         int64_t(S.bl_first[b + 1] - S.bl_first[b]));
     if (m > 65535) return fail(h, SDPC_E_PATTERN, "more than 65535 constraints");
     // ---- block arrays
     std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size());

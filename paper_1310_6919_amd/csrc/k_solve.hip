@@ -16,8 +16,11 @@
 //             substitution restricted to those rows is self-contained; values
 //             still read by lower blocks stay in LDS slots.
 // The diagonal blocks are applied through their explicit inverses, so each
-// block step is two small dense products.  Panels are staged through LDS.
-// Finally the lower triangle is mirrored to make the output symmetric.
+// block step is two small dense products.  Panels and inverses are double
+// buffered in LDS: the next block's are loaded into registers while the current
+// block is processed, so a walk pays one memory latency at its start instead of
+// one per block.  Finally the lower triangle is mirrored to make the output
+// symmetric.
 #include "kernels.h"
 
 namespace sdpc {
@@ -25,46 +28,124 @@ namespace sdpc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPanelMax = 4096;   // h * w doubles of one staged panel
+constexpr int kPanelMax = 4096;                       // h * w doubles of one panel (enforced at analysis)
+constexpr int kDinvMax = 32 * 32;                     // w * w doubles of one diagonal inverse
+constexpr int kPanelPer = kPanelMax / kThreads;       // panel values per thread in flight
+constexpr int kDinvPer = kDinvMax / kThreads;         // inverse values per thread in flight
+
+struct BlockDesc {
+    int F, w, h;
+    int64_t r0;
+    const double *P, *D;
+};
+
+__device__ inline BlockDesc block_desc(int b, const int *bl_first, const int64_t *bl_rptr, const int64_t *bl_off,
+                                       const int64_t *bl_dinv, const double *L, const double *Dinv) {
+    BlockDesc d;
+    d.F = bl_first[b];
+    d.w = bl_first[b + 1] - d.F;
+    d.r0 = bl_rptr[b];
+    d.h = int(bl_rptr[b + 1] - d.r0);
+    d.P = L + bl_off[b];
+    d.D = Dinv + bl_dinv[b];
+    return d;
+}
+
+// Loads of a block's panel and inverse into registers (issued, not waited for).
+__device__ inline void fetch_block(const BlockDesc &d, double (&rp)[kPanelPer], double (&rd)[kDinvPer]) {
+    const int hw = d.h * d.w, ww = d.w * d.w;
+#pragma unroll
+    for (int u = 0; u < kPanelPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+        rp[u] = i < hw ? d.P[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kDinvPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+        rd[u] = i < ww ? d.D[i] : 0.0;
+    }
+}
+
+__device__ inline void put_block(const BlockDesc &d, const double (&rp)[kPanelPer], const double (&rd)[kDinvPer],
+                                 double *Pn, double *Dn) {
+    const int hw = d.h * d.w, ww = d.w * d.w;
+#pragma unroll
+    for (int u = 0; u < kPanelPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+        if (i < hw) Pn[i] = rp[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kDinvPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+        if (i < ww) Dn[i] = rd[u];
+    }
+}
 
 template <int T>
 __global__ void __launch_bounds__(kThreads)
-k_inv_solve(int n, int nb, int maxw, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
             const int64_t *__restrict__ bl_off, const int *__restrict__ bl_subfirst,
             const int *__restrict__ bl_fslot, const int *__restrict__ bl_bslot,
             const int64_t *__restrict__ bl_dinv, const int *__restrict__ col_block, int nfwd, int nbwd,
             const double *__restrict__ L, const double *__restrict__ Dinv, double *__restrict__ out) {
     extern __shared__ double sm[];
-    double *Pn = sm;                                  // kPanelMax
-    double *Dn = Pn + kPanelMax;                      // maxw * maxw
-    double *accf = Dn + maxw * maxw;                  // nfwd * T
-    double *accb = accf + nfwd * T;                   // nbwd * T
-    double *v = accb + nbwd * T;                      // maxw * T
-    double *xo = v + maxw * T;                        // maxw * T
+    double *Pbuf[2] = {sm, sm + pcap};                       // pcap >= every h * w
+    double *Dbuf[2] = {sm + 2 * pcap, sm + 2 * pcap + maxw * maxw};
+    double *accf = sm + 2 * pcap + 2 * maxw * maxw;          // nfwd * T
+    double *accb = accf + nfwd * T;                          // nbwd * T
+    double *v = accb + nbwd * T;                             // maxw * T
+    double *xo = v + maxw * T;                               // maxw * T
+    int *slots[2] = {reinterpret_cast<int *>(xo + maxw * T), reinterpret_cast<int *>(xo + maxw * T) + maxh};
     constexpr int RG = kThreads / T;
     const int tid = threadIdx.x;
     const int tc = tid % T;
     const int tr = tid / T;
     const int k0 = blockIdx.x * T;
     const int kend = min(n, k0 + T);
-    const bool colok = (k0 + tc) < n;
-    double *outc = out + int64_t(n) * (k0 + tc);
     for (int i = tid; i < (nfwd + nbwd) * T; i += kThreads) accf[i] = 0.0;
     const int b0 = col_block[k0];
-    __syncthreads();
+    // a block takes part in the forward walk only if its elimination subtree meets the tile
+    auto active = [&](int b) {
+        const int F = bl_first[b], w = bl_first[b + 1] - F;
+        return !(bl_subfirst[b] > kend - 1 || F + w - 1 < k0);
+    };
+    auto next_active = [&](int b) {
+        for (++b; b < nb; ++b)
+            if (active(b)) return b;
+        return nb;
+    };
+    double rp[kPanelPer], rd[kDinvPer];
     // ------------------------------------------------------------ forward
-    for (int b = b0; b < nb; ++b) {
-        const int F = bl_first[b];
-        const int w = bl_first[b + 1] - F;
-        if (bl_subfirst[b] > kend - 1 || F + w - 1 < k0) continue;   // subtree misses the tile
-        const int64_t r0 = bl_rptr[b];
-        const int h = int(bl_rptr[b + 1] - r0);
-        const double *P = L + bl_off[b];
-        const double *D = Dinv + bl_dinv[b];
-        stage_lds<8>(Pn, P, h * w);
-        stage_lds<4>(Dn, D, w * w);
+    int cur = 0;
+    int b = active(b0) ? b0 : next_active(b0);
+    if (b < nb) {
+        const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+        fetch_block(d, rp, rd);
+        put_block(d, rp, rd, Pbuf[0], Dbuf[0]);
+        for (int i = tid; i < d.h; i += kThreads) slots[0][i] = bl_fslot[d.r0 + i];
+    }
+    __syncthreads();
+    // Each dense product of a block step is computed in 2 x 2 register blocks
+    // (two rows, two right-hand sides) so that every pair of operands read from LDS
+    // feeds four multiply-adds.  The inverse D^{-1} of a diagonal block is stored
+    // lower triangular with explicit zeros above the diagonal, so its products can
+    // run over all w columns with a uniform bound.
+    constexpr int TP = T / 2;
+    while (b < nb) {
+        const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+        const int bn = next_active(b);
+        BlockDesc dn{};
+        if (bn < nb) {
+            dn = block_desc(bn, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+            fetch_block(dn, rp, rd);   // in flight during this block's work
+        }
+        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
+        const int *fsl = slots[cur];
+        const int F = d.F, w = d.w, h = d.h, hw = h - w;
+        int fsn = -1;   // slot id of the next block's row tid, loaded with its panel
+        if (bn < nb && tid < dn.h) fsn = bl_fslot[dn.r0 + tid];
         for (int i = tr; i < w; i += RG) {
-            const int fs = bl_fslot[r0 + i];
+            const int fs = fsl[i];
             double val = 0.0;
             if (fs >= 0) {
                 val = accf[fs * T + tc];
@@ -74,50 +155,149 @@ k_inv_solve(int n, int nb, int maxw, const int *__restrict__ bl_first, const int
             v[i * T + tc] = val;
         }
         __syncthreads();
-        for (int i = tr; i < w; i += RG) {
-            double s = 0.0;
-            for (int j = 0; j <= i; ++j) s += Dn[i + w * j] * v[j * T + tc];
-            xo[i * T + tc] = s;
-            if (colok) outc[F + i] = s;
+        // xo = D^{-1} v (w x T), written to the output columns as well
+        for (int blk = tid; blk < ((w + 1) / 2) * TP; blk += kThreads) {
+            const int i0 = 2 * (blk / TP), c0 = 2 * (blk % TP), i1 = i0 + 1;
+            const bool r1 = i1 < w;
+            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < w; ++j) {
+                const double d0 = Dn[i0 + w * j], d1 = r1 ? Dn[i1 + w * j] : 0.0;
+                const double v0 = v[j * T + c0], v1 = v[j * T + c0 + 1];
+                s00 = fma(d0, v0, s00);
+                s01 = fma(d0, v1, s01);
+                s10 = fma(d1, v0, s10);
+                s11 = fma(d1, v1, s11);
+            }
+            xo[i0 * T + c0] = s00;
+            xo[i0 * T + c0 + 1] = s01;
+            if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i0] = s00;
+            if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i0] = s01;
+            if (r1) {
+                xo[i1 * T + c0] = s10;
+                xo[i1 * T + c0 + 1] = s11;
+                if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i1] = s10;
+                if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i1] = s11;
+            }
         }
         __syncthreads();
-        for (int a = tr; a < h - w; a += RG) {
-            double s = 0.0;
-            for (int j = 0; j < w; ++j) s += Pn[(w + a) + h * j] * xo[j * T + tc];
-            const int fs = bl_fslot[r0 + w + a];
-            accf[fs * T + tc] -= s;
+        // pending updates of the rows below the block: acc(U) -= P21 xo
+        for (int blk = tid; blk < ((hw + 1) / 2) * TP; blk += kThreads) {
+            const int a0 = 2 * (blk / TP), c0 = 2 * (blk % TP), a1 = a0 + 1;
+            const bool r1 = a1 < hw;
+            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < w; ++j) {
+                const double p0 = Pn[(w + a0) + h * j], p1 = r1 ? Pn[(w + a1) + h * j] : 0.0;
+                const double x0 = xo[j * T + c0], x1 = xo[j * T + c0 + 1];
+                s00 = fma(p0, x0, s00);
+                s01 = fma(p0, x1, s01);
+                s10 = fma(p1, x0, s10);
+                s11 = fma(p1, x1, s11);
+            }
+            const int f0 = fsl[w + a0];
+            accf[f0 * T + c0] -= s00;
+            accf[f0 * T + c0 + 1] -= s01;
+            if (r1) {
+                const int f1 = fsl[w + a1];
+                accf[f1 * T + c0] -= s10;
+                accf[f1 * T + c0 + 1] -= s11;
+            }
+        }
+        if (bn < nb) {
+            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
+            if (tid < dn.h) slots[cur ^ 1][tid] = fsn;
         }
         __syncthreads();
+        cur ^= 1;
+        b = bn;
     }
     // ------------------------------------------------------------ backward
-    for (int b = nb - 1; b >= b0; --b) {
-        const int F = bl_first[b];
-        const int w = bl_first[b + 1] - F;
-        const bool fwd_active = !(bl_subfirst[b] > kend - 1 || F + w - 1 < k0);
-        const int64_t r0 = bl_rptr[b];
-        const int h = int(bl_rptr[b + 1] - r0);
-        const double *P = L + bl_off[b];
-        const double *D = Dinv + bl_dinv[b];
-        stage_lds<8>(Pn, P, h * w);
-        stage_lds<4>(Dn, D, w * w);
-        __syncthreads();
-        for (int j = tr; j < w; j += RG) {
-            double s = (fwd_active && colok) ? outc[F + j] : 0.0;
-            for (int a = 0; a < h - w; ++a) {
-                const int bs = bl_bslot[r0 + w + a];
-                s -= Pn[(w + a) + h * j] * accb[bs * T + tc];
+    b = nb - 1;
+    {
+        const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+        fetch_block(d, rp, rd);
+        put_block(d, rp, rd, Pbuf[cur], Dbuf[cur]);
+        for (int i = tid; i < d.h; i += kThreads) slots[cur][i] = bl_bslot[d.r0 + i];
+    }
+    __syncthreads();
+    for (; b >= b0; --b) {
+        const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+        BlockDesc dn{};
+        int bsn = -1;
+        if (b > b0) {
+            dn = block_desc(b - 1, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
+            fetch_block(dn, rp, rd);
+            if (tid < dn.h) bsn = bl_bslot[dn.r0 + tid];
+        }
+        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
+        const int *bsl = slots[cur];
+        const int F = d.F, w = d.w, h = d.h, hw = h - w;
+        const bool fwd_active = active(b);
+        // v = z - P21^T acc(U), with z the forward result of the block (zero if inactive)
+        for (int blk = tid; blk < ((w + 1) / 2) * TP; blk += kThreads) {
+            const int j0 = 2 * (blk / TP), c0 = 2 * (blk % TP), j1 = j0 + 1;
+            const bool r1 = j1 < w;
+            const bool ok0 = fwd_active && k0 + c0 < n, ok1 = fwd_active && k0 + c0 + 1 < n;
+            double s00 = ok0 ? out[int64_t(n) * (k0 + c0) + F + j0] : 0.0;
+            double s01 = ok1 ? out[int64_t(n) * (k0 + c0 + 1) + F + j0] : 0.0;
+            double s10 = (r1 && ok0) ? out[int64_t(n) * (k0 + c0) + F + j1] : 0.0;
+            double s11 = (r1 && ok1) ? out[int64_t(n) * (k0 + c0 + 1) + F + j1] : 0.0;
+#pragma unroll 8
+            for (int a = 0; a < hw; ++a) {
+                const double *q = accb + bsl[w + a] * T + c0;
+                const double p0 = Pn[(w + a) + h * j0], p1 = r1 ? Pn[(w + a) + h * j1] : 0.0;
+                const double q0 = q[0], q1 = q[1];
+                s00 = fma(-p0, q0, s00);
+                s01 = fma(-p0, q1, s01);
+                s10 = fma(-p1, q0, s10);
+                s11 = fma(-p1, q1, s11);
             }
-            v[j * T + tc] = s;
+            v[j0 * T + c0] = s00;
+            v[j0 * T + c0 + 1] = s01;
+            if (r1) {
+                v[j1 * T + c0] = s10;
+                v[j1 * T + c0 + 1] = s11;
+            }
         }
         __syncthreads();
-        for (int i = tr; i < w; i += RG) {
-            double s = 0.0;
-            for (int j = i; j < w; ++j) s += Dn[j + w * i] * v[j * T + tc];
-            if (colok) outc[F + i] = s;
-            const int bs = bl_bslot[r0 + i];
-            if (bs >= 0) accb[bs * T + tc] = s;
+        // x = D^{-T} v (column i of D^{-1}, rows j >= i; zeros above the diagonal)
+        for (int blk = tid; blk < ((w + 1) / 2) * TP; blk += kThreads) {
+            const int i0 = 2 * (blk / TP), c0 = 2 * (blk % TP), i1 = i0 + 1;
+            const bool r1 = i1 < w;
+            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < w; ++j) {
+                const double d0 = Dn[j + w * i0], d1 = r1 ? Dn[j + w * i1] : 0.0;
+                const double v0 = v[j * T + c0], v1 = v[j * T + c0 + 1];
+                s00 = fma(d0, v0, s00);
+                s01 = fma(d0, v1, s01);
+                s10 = fma(d1, v0, s10);
+                s11 = fma(d1, v1, s11);
+            }
+            const int bs0 = bsl[i0];
+            if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i0] = s00;
+            if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i0] = s01;
+            if (bs0 >= 0) {
+                accb[bs0 * T + c0] = s00;
+                accb[bs0 * T + c0 + 1] = s01;
+            }
+            if (r1) {
+                const int bs1 = bsl[i1];
+                if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i1] = s10;
+                if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i1] = s11;
+                if (bs1 >= 0) {
+                    accb[bs1 * T + c0] = s10;
+                    accb[bs1 * T + c0 + 1] = s11;
+                }
+            }
+        }
+        if (b > b0) {
+            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
+            if (tid < dn.h) slots[cur ^ 1][tid] = bsn;
         }
         __syncthreads();
+        cur ^= 1;
     }
 }
 
@@ -139,16 +319,19 @@ __global__ void __launch_bounds__(256) k_mirror(int n, double *__restrict__ out)
     }
 }
 
+int solve_pcap(const DevStruct &d) { return int(d.max_panel < 1 ? 1 : d.max_panel); }
+
 size_t solve_lds(const DevStruct &d, int T) {
-    return sizeof(double) * (size_t(kPanelMax) + size_t(d.max_w) * d.max_w +
-                             size_t(d.nfwd + d.nbwd) * T + size_t(2) * d.max_w * T);
+    return sizeof(double) * (size_t(2) * solve_pcap(d) + size_t(2) * d.max_w * d.max_w +
+                             size_t(d.nfwd + d.nbwd) * T + size_t(2) * d.max_w * T) +
+           sizeof(int) * 2 * size_t(d.max_h);   // slot ids of the rows of the two buffered blocks
 }
 
 }  // namespace
 
 int solve_tile_width(const DevStruct &d) {
-    if (int64_t(d.max_h) * d.max_w > kPanelMax) return 0;
-    for (int T : {16, 8, 4, 2, 1})
+    if (d.max_panel > kPanelMax || d.max_w * d.max_w > kDinvMax || d.max_h > kThreads) return 0;
+    for (int T : {16, 8, 4, 2})   // products run on pairs of right-hand sides
         if (solve_lds(d, T) <= 64 * 1024) return T;
     return 0;
 }
@@ -158,16 +341,16 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L, const double 
     const int T = solve_tile_width(d);
     const int grid = (d.n + T - 1) / T;
     const size_t lds = solve_lds(d, T);
-#define SDPC_SOLVE(TT)                                                                                   \
-    hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid), dim3(kThreads), lds, st, d.n, d.nb, d.max_w,         \
-                       d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv, \
+#define SDPC_SOLVE(TT)                                                                                     \
+    hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid), dim3(kThreads), lds, st, d.n, d.nb, d.max_w, d.max_h,      \
+                       solve_pcap(d),                                                                          \
+                       d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv,   \
                        d.col_block, d.nfwd, d.nbwd, L, Dinv, out)
     switch (T) {
         case 16: SDPC_SOLVE(16); break;
         case 8: SDPC_SOLVE(8); break;
         case 4: SDPC_SOLVE(4); break;
-        case 2: SDPC_SOLVE(2); break;
-        default: SDPC_SOLVE(1); break;
+        default: SDPC_SOLVE(2); break;
     }
 #undef SDPC_SOLVE
     const int nt = (d.n + 31) / 32;
