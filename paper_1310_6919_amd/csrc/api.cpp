@@ -66,6 +66,8 @@ struct sdpc_handle {
     double last_alpha[2] = {0, 0};
     double scm_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[8]{};
+    hipStream_t side = nullptr;   // second stream (default priority): dual step alongside dX and alpha_p
+    hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
     int *pflags_f = nullptr, *pflags_b = nullptr;   // hand-over flags of the SCM Cholesky and the SCE solve
     int epoch = 0;                                    // last epoch used on those flags
     int iters = 0;
@@ -160,9 +162,13 @@ const char *sdpc_last_error(const sdpc_handle *h) { return h ? h->err.c_str() : 
 void sdpc_destroy(sdpc_handle *h) {
     if (!h) return;
     if (h->st) (void)hipStreamSynchronize(h->st);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     for (void *p : h->allocs) (void)hipFree(p);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->ev_dy) (void)hipEventDestroy(h->ev_dy);
+    if (h->ev_dual) (void)hipEventDestroy(h->ev_dual);
+    if (h->side) (void)hipStreamDestroy(h->side);
     delete h;
 }
 
@@ -524,6 +530,9 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flag_count(m) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
+    HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIPCHK(h, hipEventCreateWithFlags(&h->ev_dy, hipEventDisableTiming));
+    HIPCHK(h, hipEventCreateWithFlags(&h->ev_dual, hipEventDisableTiming));
     launch_init_point(d, h->prm.lambda0, h->X, h->Y, h->z, h->st);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -626,8 +635,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
     launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
     HIPCHK(h, hipEventRecord(h->ev[2], st));
-    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, st);
-    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, st);
+    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
     HIPCHK(h, hipEventRecord(h->ev[3], st));
     if (d.hadamard)
         launch_scm_hadamard(d, h->Xh, h->Yi, B, ldb, st);
@@ -659,14 +667,15 @@ double since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// largest alpha in (0, 1] with Y + alpha dY positive definite (parallel candidate tests)
-sdpc_status dual_step(sdpc_handle *h, double *alpha_out) {
-    launch_dual_step(h->d, h->Y, h->dY, kCand, kDualRounds, h->cand, h->flags, h->alphas, h->st);
+// Largest alpha in (0, 1] with Y + alpha dY positive definite (parallel candidate
+// tests), enqueued on the side stream once dY is ready; the caller joins ev_dual
+// on the main stream before reading the result (bracket[0]).
+sdpc_status dual_step_launch(sdpc_handle *h) {
+    HIPCHK(h, hipEventRecord(h->ev_dy, h->st));
+    HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_dy, 0));
+    launch_dual_step(h->d, h->Y, h->dY, kCand, kDualRounds, h->cand, h->flags, h->alphas, h->side);
     HIPCHK(h, hipGetLastError());
-    double br[3];
-    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 3 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(h, hipStreamSynchronize(h->st));
-    *alpha_out = br[0];
+    HIPCHK(h, hipEventRecord(h->ev_dual, h->side));
     return SDPC_OK;
 }
 
@@ -739,15 +748,19 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipEventRecord(ev[6], st));
     launch_potrs_bwd(d.m, h->B, h->ldb, h->B + d.m, h->ldb, h->dz, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[2], st));
-    // dY = G - sum dz_k A_k ; dX on E
+    // dY = G - sum dz_k A_k; the dual step runs on the side stream while dX on E and
+    // the clique-wise primal step run here
     launch_assemble(d, h->dz, 0.0, 1.0, h->G, h->dY, st);
+    TRY(dual_step_launch(h));
     launch_zcol(d, h->Xh, h->dY, h->W, st);
     launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
     launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
-    HIPCHK(h, hipEventRecord(ev[3], st));
+    HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
+    HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
     HIPCHK(h, hipGetLastError());
-    double ap = 0.0;
+    double ap = 0.0, br[3] = {0, 0, 0};
     HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     const int pf = read_flag(h, kCand + 2);
     if (pf < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
@@ -757,10 +770,8 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     (void)hipEventElapsedTime(&ms_rhs, ev[0], ev[1]);
     (void)hipEventElapsedTime(&ms_chol, ev[1], ev[2]);
     (void)hipEventElapsedTime(&ms_pm, ev[2], ev[3]);
-    const auto t0 = std::chrono::steady_clock::now();
-    double ad = 0.0;
-    TRY(dual_step(h, &ad));
-    const double ms_ad = since(t0);
+    const double ad = br[0];
+    const double ms_ad = 0.0;   // inside ms_pm: the dual step overlaps dX and alpha_p
     h->last_alpha[0] = ap;
     h->last_alpha[1] = ad;
     if (!(ap > 0.0) || !(ad > 0.0)) return fail(h, SDPC_E_STAGNATION, "step length collapsed to zero");

@@ -202,12 +202,10 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
         double a[32];
 #pragma unroll
         for (int k = 0; k < 32; ++k) a[k] = (lane < h && k < w) ? L[off + lane + int64_t(h) * k] : 0.0;
-        bool ok = true;
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             if (k < w) {   // uniform
                 const double d = lane_bcast(a[k], k);
-                ok = ok && (d > 0.0) && isfinite(d);
                 const double inv = rsqrt_newton(d);
                 const double l = (lane >= k) ? a[k] * inv : 0.0;   // row k gets sqrt(d)
                 a[k] = l;
@@ -215,9 +213,15 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
                 for (int j = k + 1; j < 32; ++j) a[j] = fma(-l, lane_bcast(l, j), a[j]);
             }
         }
-        if (!ok) {
+        // a pivot that is not positive and finite leaves a NaN (or 0 * inf) on the
+        // diagonal: one check per block instead of one per pivot inside the chain
+        double dg = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k == lane) dg = a[k];
+        if (__ballot(lane < w && !((dg > 0.0) && isfinite(dg))) != 0ull) {
             if (lane == 0) fail[cand] = b + 1;
-            return;   // uniform: the pivots were broadcast
+            return;   // uniform
         }
 #pragma unroll
         for (int k = 0; k < 32; ++k)
@@ -228,7 +232,9 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
                 *reinterpret_cast<double2 *>(Pr + (lane - w) * 32 + k) =
                     double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
         }
-        __syncthreads();
+        // one wave: its own LDS stores only need to have completed, no barrier
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
         auto dot_rows = [&](int pr) {
             const double2 *x = reinterpret_cast<const double2 *>(Pr + (pr & 0xffff) * 32);
             const double2 *y = reinterpret_cast<const double2 *>(Pr + (pr >> 16) * 32);
@@ -248,8 +254,9 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
             const int sl = up_slot[p0 + t];
             if (sl >= 0) L[sl] -= dot_rows(up_pair[p0 + t]);
         }
+        // the next block's loads must see this block's stores (other lanes' included)
         __threadfence_block();
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) fail[cand] = 0;
 }

@@ -87,7 +87,13 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             const int64_t *__restrict__ bl_off, const int *__restrict__ bl_subfirst,
             const int *__restrict__ bl_fslot, const int *__restrict__ bl_bslot,
             const int64_t *__restrict__ bl_dinv, const int *__restrict__ col_block, int nfwd, int nbwd,
-            const double *__restrict__ L, const double *__restrict__ Dinv, double *__restrict__ out) {
+            const double *__restrict__ L0, const double *__restrict__ Dinv0, double *__restrict__ out0,
+            const double *__restrict__ L1, const double *__restrict__ Dinv1, double *__restrict__ out1) {
+    // blockIdx.y picks one of two independent factors (they share the block layout),
+    // so both inverses are formed by one launch and its workgroups interleave
+    const double *L = blockIdx.y ? L1 : L0;
+    const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
+    double *out = blockIdx.y ? out1 : out0;
     extern __shared__ double sm[];
     double *Pbuf[2] = {sm, sm + pcap};                       // pcap >= every h * w
     double *Dbuf[2] = {sm + 2 * pcap, sm + 2 * pcap + maxw * maxw};
@@ -302,8 +308,9 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
 }
 
 // out(j, i) = out(i, j) for i > j, 32 x 32 tiles of the lower triangle
-__global__ void __launch_bounds__(256) k_mirror(int n, double *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_mirror(int n, double *__restrict__ out0, double *__restrict__ out1) {
     __shared__ double t[32][33];
+    double *out = blockIdx.z ? out1 : out0;
     const int bi = blockIdx.x, bj = blockIdx.y;   // tile row, tile column
     if (bi < bj) return;
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
@@ -336,16 +343,16 @@ int solve_tile_width(const DevStruct &d) {
     return 0;
 }
 
-void launch_inverse_by_solves(const DevStruct &d, const double *L, const double *Dinv, double *out,
-                              hipStream_t st) {
+void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
+                              const double *L1, const double *Dinv1, double *out1, hipStream_t st) {
     const int T = solve_tile_width(d);
     const int grid = (d.n + T - 1) / T;
+    const int nf = L1 ? 2 : 1;
     const size_t lds = solve_lds(d, T);
 #define SDPC_SOLVE(TT)                                                                                     \
-    hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid), dim3(kThreads), lds, st, d.n, d.nb, d.max_w, d.max_h,      \
-                       solve_pcap(d),                                                                          \
-                       d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv,   \
-                       d.col_block, d.nfwd, d.nbwd, L, Dinv, out)
+    hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid, nf), dim3(kThreads), lds, st, d.n, d.nb, d.max_w, d.max_h, \
+                       solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_bslot,   \
+                       d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0, out0, L1, Dinv1, out1)
     switch (T) {
         case 16: SDPC_SOLVE(16); break;
         case 8: SDPC_SOLVE(8); break;
@@ -354,7 +361,7 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L, const double 
     }
 #undef SDPC_SOLVE
     const int nt = (d.n + 31) / 32;
-    hipLaunchKernelGGL(k_mirror, dim3(nt, nt), dim3(256), 0, st, d.n, out);
+    hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
 }
 
 }  // namespace sdpc

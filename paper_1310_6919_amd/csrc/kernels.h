@@ -125,8 +125,9 @@ void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *
 
 // ---- sparse substitutions (k_solve.hip): out = (L L^T)^{-1}, n x n, full symmetric
 int solve_tile_width(const DevStruct &d);
-void launch_inverse_by_solves(const DevStruct &d, const double *L, const double *Dinv, double *out,
-                              hipStream_t st);
+// out_f = L_f^{-T} L_f^{-1} (dense n x n) for one or two factors (L1 == nullptr: one)
+void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
+                              const double *L1, const double *Dinv1, double *out1, hipStream_t st);
 
 // ---- Schur complement (k_scm.hip)
 void launch_scm_hadamard(const DevStruct &d, const double *Xh, const double *Yi, double *B,
