@@ -31,8 +31,12 @@ using namespace sdpc;
 
 namespace {
 
-constexpr int kCand = 1024;      // dual step-length candidates per round (one wave each, four per CU)
-constexpr int kDualRounds = 2;   // log grid (ratio 1.018), then one even refinement: ~2e-5 relative
+// Dual step: round 0 tests 1024 log-spaced points (neighbours 1.8% apart) and the
+// gamma twin of alpha = 1; round 1 tests 256 even points inside the bracket
+// (relative spacing ~7e-5) and their 256 gamma twins.  One wave per candidate.
+constexpr int kDualRounds = 2;
+constexpr int kDualTest[kDualRounds] = {1024, 256};
+constexpr int kCand = 1025;      // the most candidates of a round
 
 struct Timer {
     hipEvent_t a{}, b{};
@@ -70,6 +74,7 @@ struct sdpc_handle {
     hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
     int *pflags_f = nullptr, *pflags_b = nullptr;   // hand-over flags of the SCM Cholesky and the SCE solve
     int epoch = 0;                                    // last epoch used on those flags
+    int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
     int iters = 0;
 };
 
@@ -624,12 +629,18 @@ int read_flag(sdpc_handle *h, int idx) {
 }
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
-sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, double *B, int64_t ldb, bool factor) {
+sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, double *B, int64_t ldb, bool factor,
+                      bool reuse_factor = false) {
     DevStruct &d = h->d;
     hipStream_t st = h->st;
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
     HIPCHK(h, hipEventRecord(h->ev[0], st));
-    launch_sn_chol(d, Y, h->N, h->flags, st);
+    if (reuse_factor && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
+        HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
+                                 size_t(d.nslot) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+        launch_sn_chol(d, Y, h->N, h->flags, st);
+    h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
     HIPCHK(h, hipEventRecord(h->ev[1], st));
     launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
@@ -673,7 +684,8 @@ double since(std::chrono::steady_clock::time_point t0) {
 sdpc_status dual_step_launch(sdpc_handle *h) {
     HIPCHK(h, hipEventRecord(h->ev_dy, h->st));
     HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_dy, 0));
-    launch_dual_step(h->d, h->Y, h->dY, kCand, kDualRounds, h->cand, h->flags, h->alphas, h->side);
+    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->flags, h->alphas,
+                     h->side);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipEventRecord(h->ev_dual, h->side));
     return SDPC_OK;
@@ -731,7 +743,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
         return SDPC_OK;
     }
     const double bm = it.beta * it.mu;
-    TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false));
+    TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false, true));
     double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
     hipEvent_t *ev = h->ev;
     HIPCHK(h, hipEventRecord(ev[0], st));
@@ -758,9 +770,9 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
     HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
     HIPCHK(h, hipGetLastError());
-    double ap = 0.0, br[3] = {0, 0, 0};
+    double ap = 0.0, br[4] = {0, 0, 0, -1};
     HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     const int pf = read_flag(h, kCand + 2);
     if (pf < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
@@ -778,6 +790,8 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     const double gm = h->prm.gamma;
     launch_axpy_E(d, h->X, h->dX, nullptr, 0, gm * ap, st);
     launch_axpy_E(d, h->Y, h->dY, nullptr, 0, gm * ad, st);
+    // the dual step formed the factor of exactly this Y (same fma, same coefficient)
+    h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
     launch_axpy_vec(d.m, h->z, h->dz, nullptr, 0, gm * ad, st);
     HIPCHK(h, hipGetLastError());
     h->iters++;
@@ -807,6 +821,7 @@ sdpc_status sdpc_reset(sdpc_handle *h) {
     launch_init_point(h->d, h->prm.lambda0, h->X, h->Y, h->z, h->st);
     HIPCHK(h, hipGetLastError());
     h->iters = 0;
+    h->next_cand = -1;
     return SDPC_OK;
 }
 
@@ -921,6 +936,7 @@ sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double 
     launch_mask_E(h->d, h->X, h->st);
     launch_mask_E(h->d, h->Y, h->st);
     HIPCHK(h, hipGetLastError());
+    h->next_cand = -1;
     return SDPC_OK;
 }
 

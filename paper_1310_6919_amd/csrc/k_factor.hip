@@ -26,21 +26,26 @@ namespace {
 
 constexpr int kCholThreads = 256;
 
-// Candidate step length of the dual positive-definiteness test: round 0 is a
-// logarithmic grid 1e-8 .. 1; later rounds are an even grid inside the bracket
-// (lo, hi) left by the previous round.
-__device__ inline double cand_alpha(int cand, int K, int round, const double *bracket) {
-    if (round == 0) return pow(10.0, -8.0 * double(K - 1 - cand) / double(K - 1));
-    return bracket[0] + (bracket[1] - bracket[0]) * double(cand + 1) / double(K + 1);
+// Candidate step lengths of the dual positive-definiteness test.  Candidates
+// c < ntest are the test points: round 0 is a logarithmic grid 1e-8 .. 1, later
+// rounds an even grid inside the bracket (lo, hi) left by the previous round.
+// Candidates c >= ntest are twins gamma * t of test points t: in round 0 one
+// twin of t = 1, in later rounds one twin per test point.  The twin of the step
+// finally taken is the factor of the next iterate Y + gamma alpha dY.
+__device__ inline double cand_alpha(int c, int ntest, int round, double gamma, const double *bracket) {
+    const bool twin = c >= ntest;
+    const int t = twin ? (round == 0 ? ntest - 1 : c - ntest) : c;
+    const double a = (round == 0) ? pow(10.0, -8.0 * double(ntest - 1 - t) / double(ntest - 1))
+                                  : bracket[0] + (bracket[1] - bracket[0]) * double(t + 1) / double(ntest + 1);
+    return twin ? gamma * a : a;
 }
-
 
 __global__ void __launch_bounds__(kCholThreads)
 k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
           const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
           const int *__restrict__ up_pair, const int *__restrict__ up_slot, const double *__restrict__ Y,
-          const double *__restrict__ dY, const double *__restrict__ bracket, int round, double *__restrict__ Lbase,
-          int64_t stride, int *__restrict__ fail) {
+          const double *__restrict__ dY, const double *__restrict__ bracket, int round, int ntest, double gamma,
+          double *__restrict__ Lbase, int64_t stride, int *__restrict__ fail) {
     extern __shared__ double P[];
     __shared__ TileLds<64, 32> tsh;   // pivot columns of a panel with at most 64 rows
     __shared__ double colw[32];  // scaled pivot column (block width <= 32), tall panels
@@ -49,13 +54,12 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
     double *L = Lbase + cand * stride;
     double al = 0.0;
     if (dY) {
-        // round 0: a logarithmic grid 1e-8 .. 1; later rounds: an even grid inside
-        // the bracket (lo, hi) left by the previous round (bracket[2] != 0: settled)
+        // the candidate's step length (bracket[2] != 0: settled, nothing to test)
         if (round > 0 && bracket[2] != 0.0) {
             if (tid == 0) fail[cand] = 0;
             return;
         }
-        al = cand_alpha(cand, gridDim.x, round, bracket);
+        al = cand_alpha(cand, ntest, round, gamma, bracket);
     }
     // padding slots of the inputs are ignored (the factor stores an exact zero there)
     for (int64_t s = tid; s < nslot; s += blockDim.x)
@@ -150,11 +154,11 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
 // candidate per blockIdx.y; with dY == nullptr a single copy of Y.
 __global__ void __launch_bounds__(256)
 k_cand_init(int64_t nslot, const double *__restrict__ wE, const double *__restrict__ Y,
-            const double *__restrict__ dY, const double *__restrict__ bracket, int round,
+            const double *__restrict__ dY, const double *__restrict__ bracket, int round, int ntest, double gamma,
             double *__restrict__ Lbase, int64_t stride) {
     const int cand = blockIdx.y;
     if (dY && round > 0 && bracket[2] != 0.0) return;   // settled: nothing to test
-    const double al = dY ? cand_alpha(cand, gridDim.y, round, bracket) : 0.0;
+    const double al = dY ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
     double *L = Lbase + cand * stride;
     for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot; s += int64_t(gridDim.x) * blockDim.x)
         L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? fma(al, dY[s], Y[s]) : Y[s]);
@@ -384,27 +388,36 @@ k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_ma
 }
 
 // After a round of candidate tests (fail[c] == 0: Y + a_c dY positive definite),
-// keep the longest prefix of successes and narrow bracket = (lo, hi, settled).
-__global__ void k_bracket(int K, int round, const int *__restrict__ fail, double *__restrict__ bracket) {
+// keep the longest prefix of successful test points and narrow
+// bracket = (lo, hi, settled, twin): twin is the candidate index holding the
+// factor of Y + gamma lo dY, or -1 if that factor was not formed.
+__global__ void k_bracket(int ntest, int round, double gamma, const int *__restrict__ fail,
+                          double *__restrict__ bracket) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (round > 0 && bracket[2] != 0.0) return;
     int best = -1;
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < ntest; ++c) {
         if (fail[c] != 0) break;
         best = c;
     }
-    auto cand = [&](int c) { return cand_alpha(c, K, round, bracket); };
+    auto cand = [&](int c) { return cand_alpha(c, ntest, round, gamma, bracket); };
     if (round == 0) {
-        if (best == K - 1) { bracket[0] = 1.0; bracket[1] = 1.0; bracket[2] = 1.0; return; }
-        if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 1.0; return; }
+        if (best == ntest - 1) {   // alpha = 1 passes; its twin (candidate ntest) is gamma * 1
+            bracket[0] = 1.0; bracket[1] = 1.0; bracket[2] = 1.0;
+            bracket[3] = (fail[ntest] == 0) ? double(ntest) : -1.0;
+            return;
+        }
+        if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 1.0; bracket[3] = -1.0; return; }
         const double lo = cand(best), hi = cand(best + 1);
-        bracket[0] = lo; bracket[1] = hi; bracket[2] = 0.0;
+        bracket[0] = lo; bracket[1] = hi; bracket[2] = 0.0; bracket[3] = -1.0;
         return;
     }
     const double lo = best >= 0 ? cand(best) : bracket[0];
-    const double hi = best + 1 < K ? cand(best + 1) : bracket[1];
+    const double hi = best + 1 < ntest ? cand(best + 1) : bracket[1];
+    const double twin = (best >= 0 && fail[ntest + best] == 0) ? double(ntest + best) : -1.0;
     bracket[0] = lo;
     bracket[1] = hi;
+    bracket[3] = twin;
 }
 
 __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__restrict__ v, double *out) {
@@ -430,7 +443,7 @@ int sn_init_grid(int64_t nslot) {
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st) {
     if (d.max_h <= 64) {
         hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), 1), dim3(256), 0, st, d.nslot, d.wE, Y,
-                           (const double *)nullptr, (const double *)nullptr, 0, L, int64_t(0));
+                           (const double *)nullptr, (const double *)nullptr, 0, 1, 0.0, L, int64_t(0));
         hipLaunchKernelGGL(k_sn_chol_wave, dim3(1), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st, d.nb,
                            d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
                            (const double *)nullptr, 0, L, int64_t(0), fail);
@@ -439,25 +452,28 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, h
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     hipLaunchKernelGGL(k_sn_chol, dim3(1), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
                        d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, (const double *)nullptr,
-                       (const double *)nullptr, 0, L, int64_t(0), fail);
+                       (const double *)nullptr, 0, 1, 0.0, L, int64_t(0), fail);
 }
 
-void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int ncand, int rounds, double *cand,
-                      int *fail, double *bracket, hipStream_t st) {
+int dual_step_candidates(int round, const int *ntest) { return round == 0 ? ntest[0] + 1 : 2 * ntest[round]; }
+
+void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
+                      double gamma, double *cand, int *fail, double *bracket, hipStream_t st) {
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     for (int r = 0; r < rounds; ++r) {
+        const int nc = dual_step_candidates(r, ntest);
         if (d.max_h <= 64) {
-            hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), ncand), dim3(256), 0, st, d.nslot, d.wE,
-                               Y, dY, (const double *)bracket, r, cand, d.nslot);
-            hipLaunchKernelGGL(k_sn_chol_wave, dim3(ncand), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st,
+            hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), nc), dim3(256), 0, st, d.nslot, d.wE, Y,
+                               dY, (const double *)bracket, r, ntest[r], gamma, cand, d.nslot);
+            hipLaunchKernelGGL(k_sn_chol_wave, dim3(nc), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st,
                                d.nb, d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
                                (const double *)bracket, r, cand, d.nslot, fail);
         } else {
-            hipLaunchKernelGGL(k_sn_chol, dim3(ncand), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE,
-                               d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY,
-                               (const double *)bracket, r, cand, d.nslot, fail);
+            hipLaunchKernelGGL(k_sn_chol, dim3(nc), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
+                               d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket,
+                               r, ntest[r], gamma, cand, d.nslot, fail);
         }
-        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, ncand, r, (const int *)fail, bracket);
+        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, ntest[r], r, gamma, (const int *)fail, bracket);
     }
 }
 

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
 __global__ void k_axpy(int64_t len, double *__restrict__ x, const double *__restrict__ dx, double coef) {
     for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < len;
          s += int64_t(gridDim.x) * blockDim.x)
-        x[s] += coef * dx[s];
+        x[s] = fma(coef, dx[s], x[s]);   // the same rounding as the dual-step candidates
 }
 
 __global__ void k_init(int64_t nslot, const double *__restrict__ wE, double lambda, double *X, double *Y,

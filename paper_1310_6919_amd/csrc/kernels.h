@@ -110,11 +110,15 @@ void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
 // ---- factorisations (k_factor.hip)
 // Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st);
-// largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of ncand
-// parallel factorisations (log grid, then even grids inside the bracket); the result is
-// bracket[0] (a lower bound; bracket[1] an upper bound), all on the device
-void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int ncand, int rounds,
-                      double *cand, int *fail, double *bracket, hipStream_t st);
+// largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of
+// parallel factorisations of ntest[r] test points (log grid, then even grids inside
+// the bracket) plus their gamma twins; the result is bracket[0] (a lower bound;
+// bracket[1] an upper bound), bracket[3] the candidate holding the factor of
+// Y + gamma bracket[0] dY (or -1), all on the device
+void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
+                      double gamma, double *cand, int *fail, double *bracket, hipStream_t st);
+// candidates launched in a round (test points and their gamma twins)
+int dual_step_candidates(int round, const int *ntest);
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,

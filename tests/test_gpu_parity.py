@@ -39,6 +39,8 @@ CASES = {
     "band_ragged": lambda: sdpgen.maxcut_band(333, 7, 0.7, 2),
     "normmin": lambda: sdpgen.normmin(100, 10, 8, 0),
     "random_sdp": lambda: sdpgen.random_sparse_sdp(45, 20, seed=4),
+    # cliques of 51 and storage blocks of 82 rows: the Y factor's tall-panel kernel
+    "band_wide": lambda: sdpgen.maxcut_band(260, 50, 0.9, 5),
 }
 
 
@@ -235,7 +237,8 @@ def test_solve_cfg1_matches_golden(seed):
     h.close()
 
 
-@pytest.mark.parametrize("name,tol", [("cfg1", 1e-7), ("cfg1", 1e-9), ("normmin", 1e-8), ("random_sdp", 1e-8)])
+@pytest.mark.parametrize("name,tol", [("cfg1", 1e-7), ("cfg1", 1e-9), ("normmin", 1e-8), ("random_sdp", 1e-8),
+                                      ("band_wide", 1e-8)])
 def test_solve_matches_mc_oracle(name, tol):
     """The whole trajectory against the matrix-completion oracle (same method,
     same E, same step rules): iteration count, objective, and z to 1e-6."""
