@@ -65,16 +65,19 @@ struct sdpc_handle {
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
-    int *flags = nullptr;   // [0..kCand) sn_chol, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2] potrf
+    int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
+                            // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
     int64_t ldb = 0;
     double last_alpha[2] = {0, 0};
     double scm_ms[5] = {0, 0, 0, 0, 0};
-    hipEvent_t ev[8]{};
+    hipEvent_t ev[8]{};    // phases of an iteration
+    hipEvent_t evs[6]{};   // phases of the SCM evaluation
     hipStream_t side = nullptr;   // second stream (default priority): dual step alongside dX and alpha_p
     hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
     int *pflags_f = nullptr, *pflags_b = nullptr;   // hand-over flags of the SCM Cholesky and the SCE solve
     int epoch = 0;                                    // last epoch used on those flags
     int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
+    bool xside_ready = false;   // Lhat, its diagonal inverses and X^ already belong to the current X
     int iters = 0;
 };
 
@@ -170,6 +173,8 @@ void sdpc_destroy(sdpc_handle *h) {
     if (h->side) (void)hipStreamSynchronize(h->side);
     for (void *p : h->allocs) (void)hipFree(p);
     for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : h->evs)
         if (e) (void)hipEventDestroy(e);
     if (h->ev_dy) (void)hipEventDestroy(h->ev_dy);
     if (h->ev_dual) (void)hipEventDestroy(h->ev_dual);
@@ -535,6 +540,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flag_count(m) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
+    for (auto &e : h->evs) HIPCHK(h, hipEventCreate(&e));
     HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     HIPCHK(h, hipEventCreateWithFlags(&h->ev_dy, hipEventDisableTiming));
     HIPCHK(h, hipEventCreateWithFlags(&h->ev_dual, hipEventDisableTiming));
@@ -629,49 +635,74 @@ int read_flag(sdpc_handle *h, int idx) {
 }
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
+// Flags of the phases, checked after the launch sequence has completed.
+sdpc_status check_flags(sdpc_handle *h, bool potrf) {
+    int fl[kCand + 8];
+    HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl[kCand + 5])
+        return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[kCand + 5] - 1) + ")");
+    if (fl[kCand + 1])
+        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[kCand + 1] - 1) + ")");
+    if (fl[kCand + 3])
+        return fail(h, SDPC_E_NOT_PD, "clique block of the updated Xbar not positive definite (clique " +
+                                          std::to_string(fl[kCand + 3] - 1) + ")");
+    if (fl[kCand] || fl[kCand + 4]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
+    if (potrf && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
+    if (potrf && fl[kCand + 2])
+        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
+    return SDPC_OK;
+}
+
+void read_scm_timing(sdpc_handle *h) {
+    for (int i = 0; i < 5; ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, h->evs[i], h->evs[i + 1]);
+        h->scm_ms[i] = ms;
+    }
+}
+
+// Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
+// Inside an iteration (in_step) the factor of Y may come from the dual step, the
+// X side may already have been formed at the end of the previous iteration, and
+// nothing is synchronised: the caller checks the flags once at its end.
 sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, double *B, int64_t ldb, bool factor,
-                      bool reuse_factor = false) {
+                      bool in_step = false) {
     DevStruct &d = h->d;
     hipStream_t st = h->st;
+    const bool xready = in_step && h->xside_ready;
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
-    HIPCHK(h, hipEventRecord(h->ev[0], st));
-    if (reuse_factor && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
+    HIPCHK(h, hipEventRecord(h->evs[0], st));
+    if (in_step && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
         HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
                                  size_t(d.nslot) * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
-        launch_sn_chol(d, Y, h->N, h->flags, st);
+        launch_sn_chol(d, Y, h->N, h->flags + kCand + 5, st);
     h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
-    HIPCHK(h, hipEventRecord(h->ev[1], st));
-    launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
-    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
-    HIPCHK(h, hipEventRecord(h->ev[2], st));
-    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
-    HIPCHK(h, hipEventRecord(h->ev[3], st));
+    HIPCHK(h, hipEventRecord(h->evs[1], st));
+    if (!xready) {
+        launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
+        launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
+    }
+    HIPCHK(h, hipEventRecord(h->evs[2], st));
+    if (xready)
+        launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, nullptr, nullptr, nullptr, st);
+    else
+        launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
+    h->xside_ready = false;
+    HIPCHK(h, hipEventRecord(h->evs[3], st));
     if (d.hadamard)
         launch_scm_hadamard(d, h->Xh, h->Yi, B, ldb, st);
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
-    HIPCHK(h, hipEventRecord(h->ev[4], st));
+    HIPCHK(h, hipEventRecord(h->evs[4], st));
     if (factor) launch_potrf(d.m, B, ldb, h->pflags_f, ++h->epoch, h->flags + kCand + 2, st);
-    HIPCHK(h, hipEventRecord(h->ev[5], st));
+    HIPCHK(h, hipEventRecord(h->evs[5], st));
     HIPCHK(h, hipGetLastError());
+    if (in_step) return SDPC_OK;
     HIPCHK(h, hipStreamSynchronize(st));
-    for (int i = 0; i < 5; ++i) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]);
-        h->scm_ms[i] = ms;
-    }
-    int fl[kCand + 8];
-    HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
-    if (fl[0]) return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[0] - 1) + ")");
-    if (fl[kCand + 1])
-        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[kCand + 1] - 1) + ")");
-    if (fl[kCand]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
-    if (factor && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky: an internal hand-over wait ran out");
-    if (factor && fl[kCand + 2])
-        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
-    return SDPC_OK;
+    read_scm_timing(h);
+    return check_flags(h, factor);
 }
 
 double since(std::chrono::steady_clock::time_point t0) {
@@ -744,7 +775,6 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     }
     const double bm = it.beta * it.mu;
     TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false, true));
-    double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
     hipEvent_t *ev = h->ev;
     HIPCHK(h, hipEventRecord(ev[0], st));
     // right-hand side: g = b - beta mu A(Y^{-1}) + A(X^ G Y^{-1})
@@ -767,33 +797,39 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     launch_zcol(d, h->Xh, h->dY, h->W, st);
     launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
     launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
+    // Step 4 for X with alpha_p still on the device, then the X side of the next
+    // iteration (Algorithm 1, Lhat's diagonal inverses, X^) while the dual step runs
+    const double gm = h->prm.gamma;
+    launch_axpy_E(d, h->X, h->dX, h->scal + 8, gm, st);
+    launch_algorithm1(d, h->X, h->Lhat, h->flags + kCand + 3, st);
+    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand + 4, st);
+    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st);
     HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
     HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
+    // Step 4 for Y and z (alpha_d = bracket[0] on the device; the same fma as the
+    // dual step's twin candidates, whose factor of the new Y is then reused)
+    launch_axpy_E(d, h->Y, h->dY, h->alphas, gm, st);
+    launch_axpy_vec(d.m, h->z, h->dz, h->alphas, gm, st);
     HIPCHK(h, hipGetLastError());
     double ap = 0.0, br[4] = {0, 0, 0, -1};
     HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipMemcpyAsync(br, h->alphas, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
-    const int pf = read_flag(h, kCand + 2);
-    if (pf < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
-    if (pf) return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite");
+    read_scm_timing(h);
+    TRY(check_flags(h, true));
+    h->xside_ready = true;
+    h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
+    const double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
     float ms_rhs = 0, ms_chol = 0, ms_pm = 0, ms_potrf = 0;
     (void)hipEventElapsedTime(&ms_potrf, ev[1], ev[6]);
     (void)hipEventElapsedTime(&ms_rhs, ev[0], ev[1]);
     (void)hipEventElapsedTime(&ms_chol, ev[1], ev[2]);
     (void)hipEventElapsedTime(&ms_pm, ev[2], ev[3]);
     const double ad = br[0];
-    const double ms_ad = 0.0;   // inside ms_pm: the dual step overlaps dX and alpha_p
+    const double ms_ad = 0.0;   // inside ms_pm: the dual step overlaps dX, alpha_p and the next X side
     h->last_alpha[0] = ap;
     h->last_alpha[1] = ad;
     if (!(ap > 0.0) || !(ad > 0.0)) return fail(h, SDPC_E_STAGNATION, "step length collapsed to zero");
-    const double gm = h->prm.gamma;
-    launch_axpy_E(d, h->X, h->dX, nullptr, 0, gm * ap, st);
-    launch_axpy_E(d, h->Y, h->dY, nullptr, 0, gm * ad, st);
-    // the dual step formed the factor of exactly this Y (same fma, same coefficient)
-    h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
-    launch_axpy_vec(d.m, h->z, h->dz, nullptr, 0, gm * ad, st);
-    HIPCHK(h, hipGetLastError());
     h->iters++;
     if (res) {
         res->t_scm_ms += t_scm + ms_rhs;
@@ -822,6 +858,7 @@ sdpc_status sdpc_reset(sdpc_handle *h) {
     HIPCHK(h, hipGetLastError());
     h->iters = 0;
     h->next_cand = -1;
+    h->xside_ready = false;
     return SDPC_OK;
 }
 
@@ -937,6 +974,7 @@ sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double 
     launch_mask_E(h->d, h->Y, h->st);
     HIPCHK(h, hipGetLastError());
     h->next_cand = -1;
+    h->xside_ready = false;
     return SDPC_OK;
 }
 

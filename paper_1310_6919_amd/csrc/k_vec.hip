@@ -101,7 +101,11 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
     }
 }
 
-__global__ void k_axpy(int64_t len, double *__restrict__ x, const double *__restrict__ dx, double coef) {
+// x += coef dx, with coef = scale * alpha[0] when alpha is given (a step length
+// still on the device), else coef = scale
+__global__ void k_axpy(int64_t len, double *__restrict__ x, const double *__restrict__ dx,
+                       const double *__restrict__ alpha, double scale) {
+    const double coef = alpha ? scale * alpha[0] : scale;
     for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < len;
          s += int64_t(gridDim.x) * blockDim.x)
         x[s] = fma(coef, dx[s], x[s]);   // the same rounding as the dual-step candidates
@@ -149,14 +153,13 @@ void launch_metrics(const DevStruct &d, const double *X, const double *Y, const 
                        d.con_val, d.b, d.wE, X, Y, z, G, scal);
 }
 
-void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double * /*alpha*/, int /*which*/,
-                   double coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, x, dx, coef);
+void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha, double scale,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, x, dx, alpha, scale);
 }
 
-void launch_axpy_vec(int m, double *x, const double *dx, const double * /*alpha*/, int /*which*/,
-                     double coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(m)), dim3(kThreads), 0, st, int64_t(m), x, dx, coef);
+void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha, double scale, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(m)), dim3(kThreads), 0, st, int64_t(m), x, dx, alpha, scale);
 }
 
 void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z, hipStream_t st) {

@@ -99,10 +99,10 @@ void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, 
 // scal[...] <- pobj, dobj, max|r|, max|G|, X.Y, also G_E (see k_vec.hip)
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z,
                     double *G, double *scal, double *work, hipStream_t st);
-void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha_scale,
-                   int which, double gamma, hipStream_t st);
-void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha_scale, int which,
-                     double gamma, hipStream_t st);
+// x += scale * alpha[0] * dx (alpha a device scalar), or x += scale * dx when alpha is null
+void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha, double scale,
+                   hipStream_t st);
+void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha, double scale, hipStream_t st);
 void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z,
                        hipStream_t st);
 void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
