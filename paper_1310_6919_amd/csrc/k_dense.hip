@@ -165,8 +165,9 @@ __device__ inline void potrf64_wave(double (&lo)[32], double (&hi)[32], double *
 
 __global__ void __launch_bounds__(256)
 k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__restrict__ flags, int epoch,
-            int *__restrict__ fail) {
-    __shared__ double S[NB * LDS_LD];   // the updated tile, row-major; later the diagonal factor, column-major
+            int *__restrict__ fail, double *__restrict__ Rinv) {
+    __shared__ double S[NB * LDS_LD];   // the updated tile, row-major; then the diagonal factor
+    __shared__ double Ai[32 * 33], Ci[32 * 33], Eb[32 * 33];   // blocks of the factor's inverse
     __shared__ double invd[NB];
     __shared__ int go;
     const int tid = threadIdx.x;
@@ -244,6 +245,7 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
     __syncthreads();
     if (diag) {
         if (tid < 64) {
+            __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
             // rows of the tile below the block's own jb rows (right-hand-side rows riding
             // along the last block) keep their values in the jb active columns: the
             // elimination then performs their forward substitution
@@ -251,13 +253,14 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
             const bool real = J0 + lane < rows;
             double lo[32], hi[32];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
+            for (int k = 0; k < 32; ++k) {   // every load is in bounds; selects afterwards
+                const double v0 = S[lane * LDS_LD + k], v1 = S[lane * LDS_LD + 32 + k];
                 const int k2 = 32 + k;
-                lo[k] = (real && k < jb) ? (k <= lane ? S[lane * LDS_LD + k] : 0.0) : (lane == k ? 1.0 : 0.0);
-                hi[k] = (real && k2 < jb) ? (k2 <= lane ? S[lane * LDS_LD + k2] : 0.0) : (lane == k2 ? 1.0 : 0.0);
+                lo[k] = (real && k < jb) ? (k <= lane ? v0 : 0.0) : (lane == k ? 1.0 : 0.0);
+                hi[k] = (real && k2 < jb) ? (k2 <= lane ? v1 : 0.0) : (lane == k2 ? 1.0 : 0.0);
             }
             __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile is in registers before S is reused
-            potrf64_wave(lo, hi, S);   // S is free again: the tile is in registers
+            potrf64_wave(lo, hi, S);               // S serves as its scratch
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
                 S[lane * LDS_LD + k] = lo[k];
@@ -268,18 +271,61 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
             const double dg = S[lane * LDS_LD + lane];
             const unsigned long long badm = __ballot(lane < jb && !((dg > 0.0) && isfinite(dg)));
             if (badm != 0ull && lane == 0) atomicCAS(fail, 0, J0 + __ffsll((long long)badm));
+            invd[lane] = 1.0 / dg;
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            // inverses of the diagonal blocks A = R(0:32, 0:32) (lanes 0..31) and
+            // C = R(32:64, 32:64) (lanes 32..63): lane j solves for column j by forward
+            // substitution (identity beyond the block's jb rows)
+            const int hb = lane >> 5, j = lane & 31, rb = 32 * hb;
+            double x[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int gi = rb + i;
+                double sacc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) sacc = fma(-S[gi * LDS_LD + rb + k], x[k], sacc);
+                x[i] = (gi < jb) ? sacc * invd[gi] : ((i == j) ? 1.0 : 0.0);   // identity beyond the block
+            }
+            double *Xo = hb ? Ci : Ai;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) Xo[i * 33 + j] = x[i];
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
-        for (int idx = tid; idx < NB * NB; idx += blockDim.x) {   // the factor back into B, lower part
-            const int i = idx % NB, k = idx / NB;
-            if (J0 + i < rows && k < jb && k <= i) B[(J0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
+        // Eb = R(32:64, 0:32) A^{-1}, then R^{-1}(32:64, 0:32) = -C^{-1} Eb; R^{-1} is
+        // stored column-major 64 x 64 with zeros above the diagonal and identity beyond jb
+        for (int o = tid; o < 32 * 32; o += blockDim.x) {
+            const int r = o / 32, c = o % 32;
+            double e = 0.0;
+            if (32 + r < jb)
+                for (int k = c; k < 32; ++k) e = fma(S[(32 + r) * LDS_LD + k], Ai[k * 33 + c], e);
+            Eb[r * 33 + c] = e;
+        }
+        __syncthreads();
+        for (int o = tid; o < NB * NB; o += blockDim.x) {
+            const int i = o % NB, k = o / NB;   // column-major: consecutive threads, consecutive rows
+            double v;
+            if (i < 32) v = (k < 32) ? Ai[i * 33 + k] : 0.0;
+            else if (k >= 32) v = Ci[(i - 32) * 33 + (k - 32)];
+            else {
+                double f = 0.0;
+                for (int q = 0; q <= i - 32; ++q) f = fma(Ci[(i - 32) * 33 + q], Eb[q * 33 + k], f);
+                v = -f;
+            }
+            Rinv[i + NB * k] = v;
         }
         __threadfence();
         __syncthreads();
         if (tid == 0) flag_release(&flags[s], epoch);
+        // the factor itself back into B (off the chain: the panel tiles only need R^{-1})
+        for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
+            const int i = idx % NB, k = idx / NB;
+            if (J0 + i < rows && k < jb && k <= i) B[(J0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
+        }
         return;
     }
-    // panel tile: wait for the diagonal factor of this launch
+    // panel tile: wait for R_ss^{-1} of this launch, then X = C R_ss^{-T} on the MFMA
+    // (C row-major in S; R^{-1} column-major in global memory)
     if (tid == 0) {
         const bool ok = flag_wait(&flags[s], epoch);
         if (!ok) atomicCAS(fail, 0, -1);
@@ -288,42 +334,36 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
     __syncthreads();
     if (!go) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double cr[64];   // wave 0: row tid of the tile
-    if (tid < 64) {
+    d4 acc[2][2];
+    zero_acc(acc);
+    {
+        double a[2][16], b[2][16];
 #pragma unroll
-        for (int k = 0; k < 64; ++k) cr[k] = S[tid * LDS_LD + k];
-    }
-    __syncthreads();
-    // the diagonal factor, column-major, identity beyond jb
-    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-        const int j = idx % NB, k = idx / NB;
-        S[k * NB + j] = (j < jb && k < jb) ? (j >= k ? B[(J0 + j) + ldb * (J0 + k)] : 0.0) : (j == k ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    if (tid < NB) invd[tid] = 1.0 / S[tid * NB + tid];
-    __syncthreads();
-    if (tid < 64) {
-        // X R_ss^T = C: x_k = (c_k - sum_{j<k} x_j R(k, j)) / R(k, k), right-looking
+        for (int ks = 0; ks < 16; ++ks) {
+            const int k = 4 * ks + t.lk;
 #pragma unroll
-        for (int k = 0; k < 64; ++k) {
-            const double x = cr[k] * invd[k];
-            cr[k] = x;
-#pragma unroll
-            for (int j = k + 1; j < 64; ++j) {
-                cr[j] = fma(-x, S[k * NB + j], cr[j]);
-                if ((j - k) % 16 == 0) __builtin_amdgcn_sched_barrier(0);   // at most 16 operands in flight
+            for (int u = 0; u < 2; ++u) {
+                a[u][ks] = S[(t.qr + 16 * u + t.li) * LDS_LD + k];   // C(row, k)
+                b[u][ks] = Rinv[(t.qc + 16 * u + t.li) + NB * k];     // R^{-1}(col, k)
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_s_waitcnt(0xc07f);   // every read of the factor has returned
 #pragma unroll
-        for (int k = 0; k < 64; ++k) S[tid * LDS_LD + k] = cr[k];
+        for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[tj][ks], a[ti][ks], acc[ti][tj], 0, 0, 0);
     }
-    __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += blockDim.x) {   // the solved tile back into B
-        const int i = idx % NB, k = idx / NB;
-        if (I0 + i < rows && k < jb) B[(I0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
-    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = I0 + t.row(a), k = t.col(b, r);
+                if (gi < rows && k < jb) B[gi + ldb * (J0 + k)] = acc[a][b][r];
+            }
 }
 
 // R^T x = u, R lower (the factor left in B), u read with a stride (row m of B).
@@ -400,19 +440,23 @@ __global__ void k_scatter_strided(int m, const double *__restrict__ a, double *_
 
 int potrf_flag_count(int m) { return (m + NB - 1) / NB + 1; }
 
-void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, int *flags, int epoch, int *fail, hipStream_t st) {
+size_t potrf_work_doubles(int /*m*/) { return size_t(NB) * NB; }
+
+void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail,
+                       hipStream_t st) {
     const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
     for (int s = 0; s < T_cols; ++s) {
         const int nt = T_rows - s;
         int nbulk = 0;
         if (s >= 1)
             for (int K = s + 1; K < T_cols; ++K) nbulk += T_rows - K;
-        hipLaunchKernelGGL(k_chol_step, dim3(nt + nbulk), dim3(256), 0, st, B, ldb, m, rows, s, flags, epoch, fail);
+        hipLaunchKernelGGL(k_chol_step, dim3(nt + nbulk), dim3(256), 0, st, B, ldb, m, rows, s, flags, epoch, fail,
+                           work);
     }
 }
 
-void launch_potrf(int m, double *B, int64_t ldb, int *flags, int epoch, int *fail, hipStream_t st) {
-    launch_potrf_rows(m, m, B, ldb, flags, epoch, fail, st);
+void launch_potrf(int m, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail, hipStream_t st) {
+    launch_potrf_rows(m, m, B, ldb, work, flags, epoch, fail, st);
 }
 
 void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *u, int64_t ustride, double *x, int *flags,
