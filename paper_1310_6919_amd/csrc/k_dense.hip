@@ -274,17 +274,18 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
             invd[lane] = 1.0 / dg;
             __builtin_amdgcn_s_waitcnt(0xc07f);
             // inverses of the diagonal blocks A = R(0:32, 0:32) (lanes 0..31) and
-            // C = R(32:64, 32:64) (lanes 32..63): lane j solves for column j by forward
-            // substitution (identity beyond the block's jb rows)
+            // C = R(32:64, 32:64) (lanes 32..63): lane j forms column j by forward
+            // substitution, each row's sum split over four partial sums to shorten the
+            // dependent chain; rows beyond the block's jb rows are taken as identity rows
             const int hb = lane >> 5, j = lane & 31, rb = 32 * hb;
             double x[32];
 #pragma unroll
             for (int i = 0; i < 32; ++i) {
-                const int gi = rb + i;
-                double sacc = (i == j) ? 1.0 : 0.0;
+                double p[4] = {(i == j) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k = 0; k < i; ++k) sacc = fma(-S[gi * LDS_LD + rb + k], x[k], sacc);
-                x[i] = (gi < jb) ? sacc * invd[gi] : ((i == j) ? 1.0 : 0.0);   // identity beyond the block
+                for (int k = 0; k < i; ++k) p[k & 3] = fma(-S[(rb + i) * LDS_LD + rb + k], x[k], p[k & 3]);
+                const double sacc = (p[0] + p[1]) + (p[2] + p[3]);
+                x[i] = (rb + i < jb) ? sacc * invd[rb + i] : ((i == j) ? 1.0 : 0.0);
             }
             double *Xo = hb ? Ci : Ai;
 #pragma unroll
@@ -292,26 +293,41 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
             __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
-        // Eb = R(32:64, 0:32) A^{-1}, then R^{-1}(32:64, 0:32) = -C^{-1} Eb; R^{-1} is
-        // stored column-major 64 x 64 with zeros above the diagonal and identity beyond jb
-        for (int o = tid; o < 32 * 32; o += blockDim.x) {
-            const int r = o / 32, c = o % 32;
-            double e = 0.0;
-            if (32 + r < jb)
-                for (int k = c; k < 32; ++k) e = fma(S[(32 + r) * LDS_LD + k], Ai[k * 33 + c], e);
-            Eb[r * 33 + c] = e;
+        // R^{-1}(32:64, 0:32) = -C^{-1} (R(32:64, 0:32) A^{-1}): two 32 x 32 x 32 products on
+        // the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2)
+        {
+            const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+            const int bi = wv >> 1, bj = wv & 1;
+            const bool rowok = 32 + 16 * bi + li < jb;
+            d4 e = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int k = 4 * ks + lk;
+                const double xa = rowok ? S[(32 + 16 * bi + li) * LDS_LD + k] : 0.0;
+                const double za = Ai[k * 33 + 16 * bj + li];
+                e = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, e, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = e[r];
+            __syncthreads();
+            d4 f = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int k = 4 * ks + lk;
+                const double xa = Ci[(16 * bi + li) * 33 + k];
+                const double za = Eb[k * 33 + 16 * bj + li];
+                f = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, f, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Rinv[(32 + 16 * bi + 4 * r + lk) + NB * (16 * bj + li)] = -f[r];
         }
-        __syncthreads();
+        // the diagonal blocks and the zero block, column-major 64 x 64
         for (int o = tid; o < NB * NB; o += blockDim.x) {
-            const int i = o % NB, k = o / NB;   // column-major: consecutive threads, consecutive rows
+            const int i = o % NB, k = o / NB;   // consecutive threads, consecutive rows
+            if (i >= 32 && k < 32) continue;    // formed above
             double v;
             if (i < 32) v = (k < 32) ? Ai[i * 33 + k] : 0.0;
-            else if (k >= 32) v = Ci[(i - 32) * 33 + (k - 32)];
-            else {
-                double f = 0.0;
-                for (int q = 0; q <= i - 32; ++q) f = fma(Ci[(i - 32) * 33 + q], Eb[q * 33 + k], f);
-                v = -f;
-            }
+            else v = Ci[(i - 32) * 33 + (k - 32)];
             Rinv[i + NB * k] = v;
         }
         __threadfence();
