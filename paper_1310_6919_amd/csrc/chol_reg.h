@@ -41,6 +41,24 @@ __device__ inline double lane_bcast(double x, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+// One step of a right-looking elimination held one row per lane: a[j] -= l *
+// l(lane c0 + j) for k < j < 32.  The multipliers of the other rows arrive by
+// readlane, eight at a time ahead of their fmas, so the readlanes do not wait on
+// one another's scalar registers.
+__device__ inline void elim_step_bcast(double (&a)[32], double l, int k, int c0) {
+#pragma unroll
+    for (int j0 = k + 1; j0 < 32; j0 += 8) {
+        double lj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lj[u] = (j0 + u < 32) ? lane_bcast(l, c0 + j0 + u) : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < 32) a[j0 + u] = fma(-l, lj[u], a[j0 + u]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <int NR, int NC>
 struct TileLds {
     double col[2][NR];   // column k of the working matrix (unscaled), rows 0..NR-1

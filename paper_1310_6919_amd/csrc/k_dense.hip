@@ -118,8 +118,7 @@ __device__ inline void panel32_wave(double (&a)[32]) {
         const double inv = rsqrt_newton(d);
         const double l = (lane >= C0 + k) ? a[k] * inv : 0.0;   // row C0 + k gets sqrt(d)
         a[k] = l;
-#pragma unroll
-        for (int j = k + 1; j < 32; ++j) a[j] = fma(-l, lane_bcast(l, C0 + j), a[j]);
+        elim_step_bcast(a, l, k, C0);
     }
 }
 

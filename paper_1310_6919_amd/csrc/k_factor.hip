@@ -213,8 +213,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
                 const double inv = rsqrt_newton(d);
                 const double l = (lane >= k) ? a[k] * inv : 0.0;   // row k gets sqrt(d)
                 a[k] = l;
-#pragma unroll
-                for (int j = k + 1; j < 32; ++j) a[j] = fma(-l, lane_bcast(l, j), a[j]);
+                elim_step_bcast(a, l, k, 0);
             }
         }
         // a pivot that is not positive and finite leaves a NaN (or 0 * inf) on the
