@@ -27,6 +27,8 @@ namespace sdpc {
 
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));   // one MFMA accumulator
+
 constexpr int kThreads = 256;
 constexpr int kPanelMax = 4096;                       // h * w doubles of one panel (enforced at analysis)
 constexpr int kDinvMax = 32 * 32;                     // w * w doubles of one diagonal inverse
@@ -307,6 +309,246 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
     }
 }
 
+// Descriptor of a storage block, staged in LDS by the MFMA variant below so that
+// a walk step costs no dependent memory round trip before its panel is fetched.
+struct SolveDesc {
+    int F, w, h, sub;
+    int64_t r0, poff, doff;
+};
+
+constexpr int kRhs = 16;   // right-hand sides per workgroup on the MFMA variant
+
+// The same walks with T = 16 right-hand sides, blocks of width <= 32, and every
+// dense product of a block step on the FP64 MFMA (16 x 16 x 4; lane l supplies
+// A(l % 16, l / 16) and B(l / 16, l % 16), element r of the result is
+// C(4 r + l / 16, l % 16)).  Products whose result goes to the output columns are
+// formed transposed (right-hand side as the row index), so the 16 lanes of a row
+// group write 16 consecutive rows of one output column.
+__global__ void __launch_bounds__(kThreads)
+k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__ bl_first,
+                const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
+                const int *__restrict__ bl_subfirst, const int *__restrict__ bl_fslot,
+                const int *__restrict__ bl_bslot, const int64_t *__restrict__ bl_dinv,
+                const int *__restrict__ col_block, int nfwd, int nbwd, const double *__restrict__ L0,
+                const double *__restrict__ Dinv0, double *__restrict__ out0, const double *__restrict__ L1,
+                const double *__restrict__ Dinv1, double *__restrict__ out1) {
+    constexpr int T = kRhs;
+    const double *L = blockIdx.y ? L1 : L0;
+    const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
+    double *out = blockIdx.y ? out1 : out0;
+    extern __shared__ double sm[];
+    double *Pbuf[2] = {sm, sm + pcap};
+    double *Dbuf[2] = {sm + 2 * pcap, sm + 2 * pcap + maxw * maxw};
+    double *accf = sm + 2 * pcap + 2 * maxw * maxw;   // nfwd * T
+    double *accb = accf + nfwd * T;                   // nbwd * T
+    double *v = accb + nbwd * T;                      // maxw * T
+    double *xo = v + maxw * T;                        // maxw * T
+    SolveDesc *desc = reinterpret_cast<SolveDesc *>(xo + maxw * T);
+    int *slots[2] = {reinterpret_cast<int *>(desc + nb), reinterpret_cast<int *>(desc + nb) + maxh};
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lq = l >> 4;
+    const int tc = tid % T, tr = tid / T;
+    constexpr int RG = kThreads / T;
+    const int k0 = blockIdx.x * T;
+    const int kend = min(n, k0 + T);
+    for (int i = tid; i < (nfwd + nbwd) * T; i += kThreads) accf[i] = 0.0;
+    for (int b = tid; b < nb; b += kThreads) {
+        SolveDesc e;
+        e.F = bl_first[b];
+        e.w = bl_first[b + 1] - e.F;
+        e.r0 = bl_rptr[b];
+        e.h = int(bl_rptr[b + 1] - e.r0);
+        e.sub = bl_subfirst[b];
+        e.poff = bl_off[b];
+        e.doff = bl_dinv[b];
+        desc[b] = e;
+    }
+    __syncthreads();
+    const int b0 = col_block[k0];
+    auto active = [&](int b) {
+        const SolveDesc &e = desc[b];
+        return !(e.sub > kend - 1 || e.F + e.w - 1 < k0);
+    };
+    auto next_active = [&](int b) {
+        for (++b; b < nb; ++b)
+            if (active(b)) return b;
+        return nb;
+    };
+    auto bdesc = [&](int b) {
+        const SolveDesc &e = desc[b];
+        BlockDesc d;
+        d.F = e.F;
+        d.w = e.w;
+        d.h = e.h;
+        d.r0 = e.r0;
+        d.P = L + e.poff;
+        d.D = Dinv + e.doff;
+        return d;
+    };
+    double rp[kPanelPer], rd[kDinvPer];
+    // ------------------------------------------------------------ forward
+    int cur = 0;
+    int b = active(b0) ? b0 : next_active(b0);
+    if (b < nb) {
+        const BlockDesc d = bdesc(b);
+        fetch_block(d, rp, rd);
+        put_block(d, rp, rd, Pbuf[0], Dbuf[0]);
+        for (int i = tid; i < d.h; i += kThreads) slots[0][i] = bl_fslot[d.r0 + i];
+    }
+    __syncthreads();
+    while (b < nb) {
+        const BlockDesc d = bdesc(b);
+        const int bn = next_active(b);
+        BlockDesc dn{};
+        int fsn = -1;
+        if (bn < nb) {
+            dn = bdesc(bn);
+            fetch_block(dn, rp, rd);   // in flight during this block's work
+            if (tid < dn.h) fsn = bl_fslot[dn.r0 + tid];
+        }
+        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
+        const int *fsl = slots[cur];
+        const int F = d.F, w = d.w, h = d.h, hw = h - w;
+        const int kw = (w + 3) / 4;   // k-steps over the block's columns
+        for (int i = tr; i < w; i += RG) {
+            const int fs = fsl[i];
+            double val = 0.0;
+            if (fs >= 0) {
+                val = accf[fs * T + tc];
+                accf[fs * T + tc] = 0.0;
+            }
+            if (F + i == k0 + tc) val += 1.0;
+            v[i * T + tc] = val;
+        }
+        __syncthreads();
+        // xo = D^{-1} v, as xo^T = v^T D^{-T}: element (c, i)
+        if (wv < (w + 15) / 16) {
+            const int i = 16 * wv + li;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < kw; ++ks) {
+                const int k = 4 * ks + lq;
+                const double xa = (k < w) ? v[k * T + li] : 0.0;
+                const double za = (k < w && i < w) ? Dn[i + w * k] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
+            }
+            if (i < w) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 4 * r + lq;
+                    xo[i * T + c] = acc[r];
+                    if (k0 + c < n) out[int64_t(n) * (k0 + c) + F + i] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // pending updates of the rows below the block: acc(U) -= P21 xo, element (a, c)
+        for (int rt = wv; rt < (hw + 15) / 16; rt += 4) {
+            const int a = 16 * rt + li;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < kw; ++ks) {
+                const int k = 4 * ks + lq;
+                const double xa = (a < hw && k < w) ? Pn[(w + a) + h * k] : 0.0;
+                const double za = (k < w) ? xo[k * T + li] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ar = 16 * rt + 4 * r + lq;
+                if (ar < hw) accf[fsl[w + ar] * T + li] -= acc[r];
+            }
+        }
+        if (bn < nb) {
+            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
+            if (tid < dn.h) slots[cur ^ 1][tid] = fsn;
+        }
+        __syncthreads();
+        cur ^= 1;
+        b = bn;
+    }
+    // ------------------------------------------------------------ backward
+    b = nb - 1;
+    {
+        const BlockDesc d = bdesc(b);
+        fetch_block(d, rp, rd);
+        put_block(d, rp, rd, Pbuf[cur], Dbuf[cur]);
+        for (int i = tid; i < d.h; i += kThreads) slots[cur][i] = bl_bslot[d.r0 + i];
+    }
+    // forward result z of a block in the layout of the transposed products:
+    // element r of lane (wv, l) is z(16 wv + li, 4 r + lq); zero if the block was
+    // not on the forward walk
+    auto load_z = [&](int bb, double (&z)[4]) {
+        const SolveDesc &e = desc[bb];
+        const bool on = active(bb);
+        const int j = 16 * wv + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 4 * r + lq;
+            z[r] = (on && wv < 2 && j < e.w && k0 + c < n) ? out[int64_t(n) * (k0 + c) + e.F + j] : 0.0;
+        }
+    };
+    double zc[4], zn[4];
+    load_z(b, zc);
+    __syncthreads();
+    for (; b >= b0; --b) {
+        const BlockDesc d = bdesc(b);
+        BlockDesc dn{};
+        int bsn = -1;
+        if (b > b0) {
+            dn = bdesc(b - 1);
+            fetch_block(dn, rp, rd);
+            if (tid < dn.h) bsn = bl_bslot[dn.r0 + tid];
+            load_z(b - 1, zn);
+        }
+        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
+        const int *bsl = slots[cur];
+        const int F = d.F, w = d.w, h = d.h, hw = h - w;
+        // v = z - P21^T acc(U), as v^T = z^T - acc(U)^T P21: element (c, j)
+        if (wv < (w + 15) / 16) {
+            const int j = 16 * wv + li;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < (hw + 3) / 4; ++ks) {
+                const int a = 4 * ks + lq;
+                const double xa = (a < hw) ? accb[bsl[w + a] * T + li] : 0.0;
+                const double za = (a < hw && j < w) ? Pn[(w + a) + h * j] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
+            }
+            if (j < w) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[j * T + 4 * r + lq] = zc[r] - acc[r];
+            }
+        }
+        __syncthreads();
+        // x = D^{-T} v, as x^T = v^T D^{-1}: element (c, i)
+        if (wv < (w + 15) / 16) {
+            const int i = 16 * wv + li;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < (w + 3) / 4; ++ks) {
+                const int j = 4 * ks + lq;
+                const double xa = (j < w) ? v[j * T + li] : 0.0;
+                const double za = (j < w && i < w) ? Dn[j + w * i] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
+            }
+            if (i < w) {
+                const int bs = bsl[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 4 * r + lq;
+                    if (k0 + c < n) out[int64_t(n) * (k0 + c) + F + i] = acc[r];
+                    if (bs >= 0) accb[bs * T + c] = acc[r];
+                }
+            }
+        }
+        if (b > b0) {
+            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
+            if (tid < dn.h) slots[cur ^ 1][tid] = bsn;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zc[r] = zn[r];
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
 // out(j, i) = out(i, j) for i > j, 32 x 32 tiles of the lower triangle
 __global__ void __launch_bounds__(256) k_mirror(int n, double *__restrict__ out0, double *__restrict__ out1) {
     __shared__ double t[32][33];
@@ -334,6 +576,14 @@ size_t solve_lds(const DevStruct &d, int T) {
            sizeof(int) * 2 * size_t(d.max_h);   // slot ids of the rows of the two buffered blocks
 }
 
+size_t solve_lds_mma(const DevStruct &d) {
+    return solve_lds(d, kRhs) + sizeof(SolveDesc) * size_t(d.nb);
+}
+
+bool solve_mma_ok(const DevStruct &d) {
+    return d.max_panel <= kPanelMax && d.max_w <= 32 && d.max_h <= kThreads && solve_lds_mma(d) <= 64 * 1024;
+}
+
 }  // namespace
 
 int solve_tile_width(const DevStruct &d) {
@@ -345,9 +595,18 @@ int solve_tile_width(const DevStruct &d) {
 
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
                               const double *L1, const double *Dinv1, double *out1, hipStream_t st) {
+    const int nf = L1 ? 2 : 1;
+    const int nt = (d.n + 31) / 32;
+    if (solve_mma_ok(d)) {
+        hipLaunchKernelGGL(k_inv_solve_mma, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), solve_lds_mma(d), st,
+                           d.n, d.nb, d.max_w, d.max_h, solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off,
+                           d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0,
+                           out0, L1, Dinv1, out1);
+        hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
+        return;
+    }
     const int T = solve_tile_width(d);
     const int grid = (d.n + T - 1) / T;
-    const int nf = L1 ? 2 : 1;
     const size_t lds = solve_lds(d, T);
 #define SDPC_SOLVE(TT)                                                                                     \
     hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid, nf), dim3(kThreads), lds, st, d.n, d.nb, d.max_w, d.max_h, \
@@ -360,7 +619,6 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
         default: SDPC_SOLVE(2); break;
     }
 #undef SDPC_SOLVE
-    const int nt = (d.n + 31) / 32;
     hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
 }
 
