@@ -68,6 +68,17 @@ __device__ inline void fetch_block(const BlockDesc &d, double (&rp)[kPanelPer], 
     }
 }
 
+// The same loads with clamped indices instead of guards: no branches, so the
+// compiler's wait counting stays exact and the loads remain in flight across the
+// block step instead of being waited for at its first use of any register.
+__device__ inline void fetch_block_nb(const BlockDesc &d, double (&rp)[kPanelPer], double (&rd)[kDinvPer]) {
+    const int hw = d.h * d.w, ww = d.w * d.w;
+#pragma unroll
+    for (int u = 0; u < kPanelPer; ++u) rp[u] = d.P[min(int(threadIdx.x) + u * kThreads, hw - 1)];
+#pragma unroll
+    for (int u = 0; u < kDinvPer; ++u) rd[u] = d.D[min(int(threadIdx.x) + u * kThreads, ww - 1)];
+}
+
 __device__ inline void put_block(const BlockDesc &d, const double (&rp)[kPanelPer], const double (&rd)[kDinvPer],
                                  double *Pn, double *Dn) {
     const int hw = d.h * d.w, ww = d.w * d.w;
@@ -97,13 +108,13 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
     const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
     double *out = blockIdx.y ? out1 : out0;
     extern __shared__ double sm[];
-    double *Pbuf[2] = {sm, sm + pcap};                       // pcap >= every h * w
-    double *Dbuf[2] = {sm + 2 * pcap, sm + 2 * pcap + maxw * maxw};
+    double *const Pbuf0 = sm, *const Pbuf1 = sm + pcap;      // pcap >= every h * w
+    double *const Dbuf0 = sm + 2 * pcap, *const Dbuf1 = sm + 2 * pcap + maxw * maxw;
     double *accf = sm + 2 * pcap + 2 * maxw * maxw;          // nfwd * T
     double *accb = accf + nfwd * T;                          // nbwd * T
     double *v = accb + nbwd * T;                             // maxw * T
     double *xo = v + maxw * T;                               // maxw * T
-    int *slots[2] = {reinterpret_cast<int *>(xo + maxw * T), reinterpret_cast<int *>(xo + maxw * T) + maxh};
+    int *const slots0 = reinterpret_cast<int *>(xo + maxw * T), *const slots1 = slots0 + maxh;
     constexpr int RG = kThreads / T;
     const int tid = threadIdx.x;
     const int tc = tid % T;
@@ -129,8 +140,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
     if (b < nb) {
         const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
         fetch_block(d, rp, rd);
-        put_block(d, rp, rd, Pbuf[0], Dbuf[0]);
-        for (int i = tid; i < d.h; i += kThreads) slots[0][i] = bl_fslot[d.r0 + i];
+        put_block(d, rp, rd, Pbuf0, Dbuf0);
+        for (int i = tid; i < d.h; i += kThreads) slots0[i] = bl_fslot[d.r0 + i];
     }
     __syncthreads();
     // Each dense product of a block step is computed in 2 x 2 register blocks
@@ -147,8 +158,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             dn = block_desc(bn, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
             fetch_block(dn, rp, rd);   // in flight during this block's work
         }
-        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
-        const int *fsl = slots[cur];
+        const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
+        const int *fsl = ((cur) ? slots1 : slots0);
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
         int fsn = -1;   // slot id of the next block's row tid, loaded with its panel
         if (bn < nb && tid < dn.h) fsn = bl_fslot[dn.r0 + tid];
@@ -213,8 +224,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             }
         }
         if (bn < nb) {
-            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
-            if (tid < dn.h) slots[cur ^ 1][tid] = fsn;
+            put_block(dn, rp, rd, ((cur ^ 1) ? Pbuf1 : Pbuf0), ((cur ^ 1) ? Dbuf1 : Dbuf0));
+            if (tid < dn.h) ((cur ^ 1) ? slots1 : slots0)[tid] = fsn;
         }
         __syncthreads();
         cur ^= 1;
@@ -225,8 +236,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
     {
         const BlockDesc d = block_desc(b, bl_first, bl_rptr, bl_off, bl_dinv, L, Dinv);
         fetch_block(d, rp, rd);
-        put_block(d, rp, rd, Pbuf[cur], Dbuf[cur]);
-        for (int i = tid; i < d.h; i += kThreads) slots[cur][i] = bl_bslot[d.r0 + i];
+        put_block(d, rp, rd, ((cur) ? Pbuf1 : Pbuf0), ((cur) ? Dbuf1 : Dbuf0));
+        for (int i = tid; i < d.h; i += kThreads) ((cur) ? slots1 : slots0)[i] = bl_bslot[d.r0 + i];
     }
     __syncthreads();
     for (; b >= b0; --b) {
@@ -238,8 +249,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             fetch_block(dn, rp, rd);
             if (tid < dn.h) bsn = bl_bslot[dn.r0 + tid];
         }
-        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
-        const int *bsl = slots[cur];
+        const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
+        const int *bsl = ((cur) ? slots1 : slots0);
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
         const bool fwd_active = active(b);
         // v = z - P21^T acc(U), with z the forward result of the block (zero if inactive)
@@ -301,8 +312,8 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             }
         }
         if (b > b0) {
-            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
-            if (tid < dn.h) slots[cur ^ 1][tid] = bsn;
+            put_block(dn, rp, rd, ((cur ^ 1) ? Pbuf1 : Pbuf0), ((cur ^ 1) ? Dbuf1 : Dbuf0));
+            if (tid < dn.h) ((cur ^ 1) ? slots1 : slots0)[tid] = bsn;
         }
         __syncthreads();
         cur ^= 1;
@@ -337,14 +348,14 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
     const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
     double *out = blockIdx.y ? out1 : out0;
     extern __shared__ double sm[];
-    double *Pbuf[2] = {sm, sm + pcap};
-    double *Dbuf[2] = {sm + 2 * pcap, sm + 2 * pcap + maxw * maxw};
+    double *const Pbuf0 = sm, *const Pbuf1 = sm + pcap;
+    double *const Dbuf0 = sm + 2 * pcap, *const Dbuf1 = sm + 2 * pcap + maxw * maxw;
     double *accf = sm + 2 * pcap + 2 * maxw * maxw;   // nfwd * T
     double *accb = accf + nfwd * T;                   // nbwd * T
     double *v = accb + nbwd * T;                      // maxw * T
     double *xo = v + maxw * T;                        // maxw * T
     SolveDesc *desc = reinterpret_cast<SolveDesc *>(xo + maxw * T);
-    int *slots[2] = {reinterpret_cast<int *>(desc + nb), reinterpret_cast<int *>(desc + nb) + maxh};
+    int *const slots0 = reinterpret_cast<int *>(desc + nb), *const slots1 = slots0 + maxh;
     const int tid = threadIdx.x;
     const int wv = tid >> 6, l = tid & 63, li = l & 15, lq = l >> 4;
     const int tc = tid % T, tr = tid / T;
@@ -392,8 +403,8 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
     if (b < nb) {
         const BlockDesc d = bdesc(b);
         fetch_block(d, rp, rd);
-        put_block(d, rp, rd, Pbuf[0], Dbuf[0]);
-        for (int i = tid; i < d.h; i += kThreads) slots[0][i] = bl_fslot[d.r0 + i];
+        put_block(d, rp, rd, Pbuf0, Dbuf0);
+        for (int i = tid; i < d.h; i += kThreads) slots0[i] = bl_fslot[d.r0 + i];
     }
     __syncthreads();
     while (b < nb) {
@@ -403,11 +414,11 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         int fsn = -1;
         if (bn < nb) {
             dn = bdesc(bn);
-            fetch_block(dn, rp, rd);   // in flight during this block's work
-            if (tid < dn.h) fsn = bl_fslot[dn.r0 + tid];
+            fetch_block_nb(dn, rp, rd);   // in flight during this block's work
+            fsn = bl_fslot[dn.r0 + min(tid, dn.h - 1)];
         }
-        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
-        const int *fsl = slots[cur];
+        const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
+        const int *fsl = ((cur) ? slots1 : slots0);
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
         const int kw = (w + 3) / 4;   // k-steps over the block's columns
         for (int i = tr; i < w; i += RG) {
@@ -458,8 +469,8 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
             }
         }
         if (bn < nb) {
-            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
-            if (tid < dn.h) slots[cur ^ 1][tid] = fsn;
+            put_block(dn, rp, rd, ((cur ^ 1) ? Pbuf1 : Pbuf0), ((cur ^ 1) ? Dbuf1 : Dbuf0));
+            if (tid < dn.h) ((cur ^ 1) ? slots1 : slots0)[tid] = fsn;
         }
         __syncthreads();
         cur ^= 1;
@@ -470,8 +481,8 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
     {
         const BlockDesc d = bdesc(b);
         fetch_block(d, rp, rd);
-        put_block(d, rp, rd, Pbuf[cur], Dbuf[cur]);
-        for (int i = tid; i < d.h; i += kThreads) slots[cur][i] = bl_bslot[d.r0 + i];
+        put_block(d, rp, rd, ((cur) ? Pbuf1 : Pbuf0), ((cur) ? Dbuf1 : Dbuf0));
+        for (int i = tid; i < d.h; i += kThreads) ((cur) ? slots1 : slots0)[i] = bl_bslot[d.r0 + i];
     }
     // forward result z of a block in the layout of the transposed products:
     // element r of lane (wv, l) is z(16 wv + li, 4 r + lq); zero if the block was
@@ -480,10 +491,12 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         const SolveDesc &e = desc[bb];
         const bool on = active(bb);
         const int j = 16 * wv + li;
+        const int jc = min(j, e.w - 1);   // clamped: every load is in bounds, selects afterwards
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = 4 * r + lq;
-            z[r] = (on && wv < 2 && j < e.w && k0 + c < n) ? out[int64_t(n) * (k0 + c) + e.F + j] : 0.0;
+            const double zz = out[int64_t(n) * min(k0 + c, n - 1) + e.F + jc];
+            z[r] = (on && wv < 2 && j < e.w && k0 + c < n) ? zz : 0.0;
         }
     };
     double zc[4], zn[4];
@@ -495,12 +508,12 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         int bsn = -1;
         if (b > b0) {
             dn = bdesc(b - 1);
-            fetch_block(dn, rp, rd);
-            if (tid < dn.h) bsn = bl_bslot[dn.r0 + tid];
+            fetch_block_nb(dn, rp, rd);
+            bsn = bl_bslot[dn.r0 + min(tid, dn.h - 1)];
             load_z(b - 1, zn);
         }
-        const double *Pn = Pbuf[cur], *Dn = Dbuf[cur];
-        const int *bsl = slots[cur];
+        const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
+        const int *bsl = ((cur) ? slots1 : slots0);
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
         // v = z - P21^T acc(U), as v^T = z^T - acc(U)^T P21: element (c, j)
         if (wv < (w + 15) / 16) {
@@ -539,8 +552,8 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
             }
         }
         if (b > b0) {
-            put_block(dn, rp, rd, Pbuf[cur ^ 1], Dbuf[cur ^ 1]);
-            if (tid < dn.h) slots[cur ^ 1][tid] = bsn;
+            put_block(dn, rp, rd, ((cur ^ 1) ? Pbuf1 : Pbuf0), ((cur ^ 1) ? Dbuf1 : Dbuf0));
+            if (tid < dn.h) ((cur ^ 1) ? slots1 : slots0)[tid] = bsn;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) zc[r] = zn[r];
