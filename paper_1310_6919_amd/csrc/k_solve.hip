@@ -329,6 +329,29 @@ struct SolveDesc {
 
 constexpr int kRhs = 16;   // right-hand sides per workgroup on the MFMA variant
 
+// One 16 x 16 tile of sum_k A(row, k) B(k, col) over at most 32 values of k on
+// the FP64 MFMA.  fa(k) and fb(k) return this lane's operands for
+// k = 4 ks + l / 16 (zero where k is out of range).  All operands are read
+// first, then two accumulators take alternate k-steps, which halves the chain
+// of dependent MFMAs.
+template <typename FA, typename FB>
+__device__ inline d4 mma32(FA fa, FB fb) {
+    const int lq = (threadIdx.x & 63) >> 4;
+    double xa[8], zb[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        xa[ks] = fa(4 * ks + lq);
+        zb[ks] = fb(4 * ks + lq);
+    }
+    d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+    for (int ks = 0; ks < 8; ks += 2) {
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks], zb[ks], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks + 1], zb[ks + 1], a1, 0, 0, 0);
+    }
+    return a0 + a1;
+}
+
 // The same walks with T = 16 right-hand sides, blocks of width <= 32, and every
 // dense product of a block step on the FP64 MFMA (16 x 16 x 4; lane l supplies
 // A(l % 16, l / 16) and B(l / 16, l % 16), element r of the result is
@@ -420,28 +443,34 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
         const int *fsl = ((cur) ? slots1 : slots0);
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
-        const int kw = (w + 3) / 4;   // k-steps over the block's columns
-        for (int i = tr; i < w; i += RG) {
-            const int fs = fsl[i];
-            double val = 0.0;
-            if (fs >= 0) {
-                val = accf[fs * T + tc];
-                accf[fs * T + tc] = 0.0;
+        const int w1 = w - 1, hw1 = max(hw - 1, 0);   // clamps: operand reads stay in range
+#pragma unroll
+        for (int u = 0; u < 32 / RG; ++u) {   // w <= 32
+            const int i = tr + RG * u;
+            if (i < w) {
+                const int fs = fsl[i];
+                double val = 0.0;
+                if (fs >= 0) {
+                    val = accf[fs * T + tc];
+                    accf[fs * T + tc] = 0.0;
+                }
+                if (F + i == k0 + tc) val += 1.0;
+                v[i * T + tc] = val;
             }
-            if (F + i == k0 + tc) val += 1.0;
-            v[i * T + tc] = val;
         }
         __syncthreads();
         // xo = D^{-1} v, as xo^T = v^T D^{-T}: element (c, i)
         if (wv < (w + 15) / 16) {
-            const int i = 16 * wv + li;
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < kw; ++ks) {
-                const int k = 4 * ks + lq;
-                const double xa = (k < w) ? v[k * T + li] : 0.0;
-                const double za = (k < w && i < w) ? Dn[i + w * k] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
-            }
+            const int i = 16 * wv + li, ic = min(i, w1);
+            const d4 acc = mma32(
+                [&](int k) {
+                    const double x = v[min(k, w1) * T + li];
+                    return (k < w) ? x : 0.0;
+                },
+                [&](int k) {
+                    const double z = Dn[ic + w * min(k, w1)];
+                    return (k < w && i < w) ? z : 0.0;
+                });
             if (i < w) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -454,14 +483,16 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         __syncthreads();
         // pending updates of the rows below the block: acc(U) -= P21 xo, element (a, c)
         for (int rt = wv; rt < (hw + 15) / 16; rt += 4) {
-            const int a = 16 * rt + li;
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < kw; ++ks) {
-                const int k = 4 * ks + lq;
-                const double xa = (a < hw && k < w) ? Pn[(w + a) + h * k] : 0.0;
-                const double za = (k < w) ? xo[k * T + li] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
-            }
+            const int a = 16 * rt + li, ac = min(a, hw1);
+            const d4 acc = mma32(
+                [&](int k) {
+                    const double x = Pn[(w + ac) + h * min(k, w1)];
+                    return (a < hw && k < w) ? x : 0.0;
+                },
+                [&](int k) {
+                    const double z = xo[min(k, w1) * T + li];
+                    return (k < w) ? z : 0.0;
+                });
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ar = 16 * rt + 4 * r + lq;
@@ -517,14 +548,20 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         const int F = d.F, w = d.w, h = d.h, hw = h - w;
         // v = z - P21^T acc(U), as v^T = z^T - acc(U)^T P21: element (c, j)
         if (wv < (w + 15) / 16) {
-            const int j = 16 * wv + li;
+            const int j = 16 * wv + li, jc = min(j, w - 1), hw1 = max(hw - 1, 0);
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < (hw + 3) / 4; ++ks) {
-                const int a = 4 * ks + lq;
-                const double xa = (a < hw) ? accb[bsl[w + a] * T + li] : 0.0;
-                const double za = (a < hw && j < w) ? Pn[(w + a) + h * j] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
-            }
+            for (int a0 = 0; a0 < hw; a0 += 32)
+                acc += mma32(
+                    [&](int k) {
+                        const int a = a0 + k;
+                        const double x = accb[bsl[w + min(a, hw1)] * T + li];
+                        return (a < hw) ? x : 0.0;
+                    },
+                    [&](int k) {
+                        const int a = a0 + k;
+                        const double z = Pn[(w + min(a, hw1)) + h * jc];
+                        return (a < hw && j < w) ? z : 0.0;
+                    });
             if (j < w) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[j * T + 4 * r + lq] = zc[r] - acc[r];
@@ -533,14 +570,16 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         __syncthreads();
         // x = D^{-T} v, as x^T = v^T D^{-1}: element (c, i)
         if (wv < (w + 15) / 16) {
-            const int i = 16 * wv + li;
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < (w + 3) / 4; ++ks) {
-                const int j = 4 * ks + lq;
-                const double xa = (j < w) ? v[j * T + li] : 0.0;
-                const double za = (j < w && i < w) ? Dn[j + w * i] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, acc, 0, 0, 0);
-            }
+            const int i = 16 * wv + li, ic = min(i, w - 1);
+            const d4 acc = mma32(
+                [&](int j) {
+                    const double x = v[min(j, w - 1) * T + li];
+                    return (j < w) ? x : 0.0;
+                },
+                [&](int j) {
+                    const double z = Dn[min(j, w - 1) + w * ic];
+                    return (j < w && i < w) ? z : 0.0;
+                });
             if (i < w) {
                 const int bs = bsl[i];
 #pragma unroll
