@@ -18,8 +18,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -65,6 +67,7 @@ struct sdpc_handle {
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
+    double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
     int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
                             // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
     int64_t ldb = 0;
@@ -292,6 +295,59 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             }
         up_ptr[b + 1] = int64_t(up_pair.size());
     }
+    // ---- slots of the pending updates of the one-wave factorisation.  An entry that
+    // receives updates is alive from its first update (in block order) until its own
+    // block forms its panel; a pool slot freed at a block can be taken by an entry born
+    // at the same block (the panel is read before the block's updates are written).
+    std::vector<int> up_u(up_slot.size(), -1), slot_u(size_t(S.nslot), -1);
+    {
+        std::vector<int> born_at(size_t(S.nslot), -1), own(size_t(S.nslot), -1);
+        for (int b = 0; b < S.nb; ++b)
+            for (int64_t s = S.bl_off[b]; s < S.bl_off[b + 1]; ++s) own[s] = b;
+        for (int b = 0; b < S.nb; ++b)
+            for (int64_t t = up_ptr[b]; t < up_ptr[b + 1]; ++t)
+                if (up_slot[t] >= 0 && born_at[up_slot[t]] < 0) born_at[up_slot[t]] = b;
+        std::vector<std::vector<int>> born(S.nb), dies(S.nb);
+        int ntarget = 0;
+        for (int64_t s = 0; s < S.nslot; ++s)
+            if (born_at[s] >= 0) {
+                born[born_at[s]].push_back(int(s));
+                dies[own[s]].push_back(int(s));
+                ++ntarget;
+            }
+        std::priority_queue<int, std::vector<int>, std::greater<int>> freel;
+        int used = 0;
+        for (int b = 0; b < S.nb; ++b) {
+            for (int s : dies[b]) freel.push(slot_u[s]);
+            for (int s : born[b]) {
+                int k;
+                if (!freel.empty()) { k = freel.top(); freel.pop(); } else { k = used++; }
+                slot_u[s] = k;
+            }
+        }
+        // the pool fits when the factorisation's LDS stays within 32 KB (four waves per CU)
+        const size_t pool_lds = sizeof(double) * (size_t(S.max_h) * 32 + size_t(used));
+        d.u_pool = (pool_lds <= 32 * 1024) ? 1 : 0;
+        if (!d.u_pool) {   // one slot per target entry, in global memory
+            int k = 0;
+            for (int64_t s = 0; s < S.nslot; ++s)
+                if (born_at[s] >= 0) slot_u[s] = k++;
+        }
+        d.nU = d.u_pool ? used : ntarget;
+        std::vector<uint8_t> seen(size_t(S.nslot), 0);
+        for (int b = 0; b < S.nb; ++b)
+            for (int64_t t = up_ptr[b]; t < up_ptr[b + 1]; ++t) {
+                const int s = up_slot[t];
+                if (s < 0) continue;
+                const bool first = !seen[s];
+                seen[s] = 1;
+                up_u[t] = (slot_u[s] << 1) | (first ? 1 : 0);
+            }
+        // padding slots (stored but outside E) start from zero: -2, or -3 - slot when
+        // they receive updates (fill inside an amalgamated block)
+        for (int64_t s = 0; s < S.nslot; ++s)
+            if (!S.isE[s]) slot_u[s] = (slot_u[s] >= 0) ? -3 - slot_u[s] : -2;
+    }
     // ---- cliques
     std::vector<int64_t> cl_ptr(S.ncl + 1, 0), cl_map_ptr(S.ncl + 1, 0);
     std::vector<int> cl_rows, cl_map;
@@ -471,6 +527,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.up_ptr, up_ptr));
     TRY(upload(h, &d.up_pair, up_pair));
     TRY(upload(h, &d.up_slot, up_slot));
+    TRY(upload(h, &d.up_u, up_u));
+    TRY(upload(h, &d.slot_u, slot_u));
     TRY(upload(h, &d.col_block, S.col_block));
     TRY(upload(h, &d.slot_row, slot_row));
     TRY(upload(h, &d.slot_col, slot_col));
@@ -534,6 +592,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
+    TRY(dalloc(h, &h->ubuf, std::max<size_t>(size_t(d.nU), 1) * kCand));
     TRY(dalloc(h, &h->part, std::max(size_t(2) * dX_chunks(d) * ns, size_t(rhs_had_parts(d)) * n)));
     TRY(dalloc(h, &h->flags, kCand + 8));
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
@@ -678,7 +737,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
         HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
                                  size_t(d.nslot) * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
-        launch_sn_chol(d, Y, h->N, h->flags + kCand + 5, st);
+        launch_sn_chol(d, Y, h->N, h->ubuf, h->flags + kCand + 5, st);
     h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
     HIPCHK(h, hipEventRecord(h->evs[1], st));
@@ -717,8 +776,8 @@ double since(std::chrono::steady_clock::time_point t0) {
 sdpc_status dual_step_launch(sdpc_handle *h) {
     HIPCHK(h, hipEventRecord(h->ev_dy, h->st));
     HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_dy, 0));
-    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->flags, h->alphas,
-                     h->side);
+    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->ubuf, h->flags,
+                     h->alphas, h->side);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipEventRecord(h->ev_dual, h->side));
     return SDPC_OK;

@@ -150,62 +150,89 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
     if (tid == 0) fail[cand] = 0;
 }
 
-// L_c = Y + alpha_c dY on the slots of E (zero in padding slots), one
-// candidate per blockIdx.y; with dY == nullptr a single copy of Y.
-__global__ void __launch_bounds__(256)
-k_cand_init(int64_t nslot, const double *__restrict__ wE, const double *__restrict__ Y,
-            const double *__restrict__ dY, const double *__restrict__ bracket, int round, int ntest, double gamma,
-            double *__restrict__ Lbase, int64_t stride) {
-    const int cand = blockIdx.y;
-    if (dY && round > 0 && bracket[2] != 0.0) return;   // settled: nothing to test
-    const double al = dY ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
-    double *L = Lbase + cand * stride;
-    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nslot; s += int64_t(gridDim.x) * blockDim.x)
-        L[s] = (wE[s] == 0.0) ? 0.0 : (dY ? fma(al, dY[s], Y[s]) : Y[s]);
-}
-
 // Y = N N^T on the storage blocks by a single wave (panels of at most 64 rows and
 // 32 columns).  Lane i holds row i of the panel in registers; the pivot and the
 // scaled pivot column reach the other lanes through readlane, so the elimination
 // needs neither LDS nor barriers.  The update of the ancestors, N(U, U) -=
-// L21 L21^T, takes its operands from LDS (rows of L21, row-major) and its old
-// values are loaded before the elimination so their latency is hidden.
-// blockIdx.x selects the candidate matrix L_c prepared by k_cand_init; the
-// factor overwrites it.
-constexpr int kPrefetch = 4;   // update pairs per lane loaded ahead of the elimination
+// L21 L21^T, takes its operands from LDS (rows of L21, row-major).
+// blockIdx.x selects the candidate Y + alpha_c dY (dY == nullptr: Y itself).  The
+// candidate is never written out: a panel is formed when its block is reached,
+// from Y and dY (read one block ahead, while the previous block is factorised)
+// and the pending updates of its descendants.  Those live in slots (slot_u maps
+// a storage slot to its slot: -1 if it receives no update; on padding, which
+// starts from zero, -2 or -3 - slot); with POOL
+// the slots are a pool in LDS, reused once a panel has consumed them, otherwise
+// a per-candidate array in global memory.  The first update of a slot in block
+// order overwrites it (up_u = slot << 1 | first), so no slot needs clearing.  The
+// factor is stored (the whole panel, zeros above the diagonal) only by the
+// candidates whose factor is used afterwards: the gamma twins, or every
+// candidate when dY is null.
+constexpr int kPairsPer = 4;   // update pairs per lane loaded ahead of the elimination
 
+template <bool POOL>
 __global__ void __launch_bounds__(64)
 k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
                const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
-               const int *__restrict__ up_pair, const int *__restrict__ up_slot, const double *__restrict__ bracket,
-               int round, double *__restrict__ Lbase, int64_t stride, int *__restrict__ fail) {
-    extern __shared__ double Pr[];   // rows >= w of the factored panel, 32 doubles per row
+               const int *__restrict__ up_pair, const int *__restrict__ up_u, const int *__restrict__ slot_u,
+               const double *__restrict__ Y, const double *__restrict__ dY, const double *__restrict__ bracket,
+               int round, int ntest, double gamma, double *__restrict__ Lbase, int64_t stride,
+               double *__restrict__ Ubase, int64_t ustride, int prcap, int *__restrict__ fail) {
+    extern __shared__ double sm[];
+    double *Pr = sm;   // rows >= w of the factored panel, 32 doubles per row (prcap doubles)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
-    if (bracket && round > 0 && bracket[2] != 0.0) {
+    if (dY && round > 0 && bracket[2] != 0.0) {   // settled: nothing to test
         if (lane == 0) fail[cand] = 0;
         return;
     }
+    const double al = dY ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
+    const bool keep = !dY || cand >= ntest;   // the factor is used afterwards
     double *L = Lbase + cand * stride;
+    double *U = POOL ? sm + prcap : Ubase + cand * ustride;
+    // inputs of the next block, in flight while the current one is processed
+    // (clamped indices: every load is in bounds, the selects come later)
+    double qy[32], qdy[32];
+    int qsu[32];
+    auto issue = [&](int bb) {
+        const int ww = bl_first[bb + 1] - bl_first[bb];
+        const int hh = int(bl_rptr[bb + 1] - bl_rptr[bb]);
+        const int64_t oo = bl_off[bb] + min(lane, hh - 1);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int64_t sk = oo + int64_t(hh) * min(k, ww - 1);
+            qsu[k] = slot_u[sk];
+            qy[k] = Y[sk];
+            qdy[k] = dY ? dY[sk] : 0.0;
+        }
+    };
+    issue(0);
     for (int b = 0; b < nb; ++b) {
         const int w = bl_first[b + 1] - bl_first[b];
         const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
         const int64_t off = bl_off[b];
         const int64_t p0 = up_ptr[b];
         const int np = int(up_ptr[b + 1] - p0);
-        int ps[kPrefetch], pp[kPrefetch];
-        double old[kPrefetch];
+        int pu[kPairsPer], pp[kPairsPer];
 #pragma unroll
-        for (int m = 0; m < kPrefetch; ++m) {
-            const int t = lane + 64 * m;
-            ps[m] = (t < np) ? up_slot[p0 + t] : -1;
-            pp[m] = (t < np) ? up_pair[p0 + t] : 0;
+        for (int m = 0; m < kPairsPer; ++m) {
+            const int t = min(lane + 64 * m, max(np - 1, 0));
+            pu[m] = (np > 0) ? up_u[p0 + t] : -1;
+            pp[m] = (np > 0) ? up_pair[p0 + t] : 0;
+            if (lane + 64 * m >= np) pu[m] = -1;
         }
-#pragma unroll
-        for (int m = 0; m < kPrefetch; ++m) old[m] = (ps[m] >= 0) ? L[ps[m]] : 0.0;
+        // the panel of the candidate: Y + alpha dY plus the pending updates
         double a[32];
+        int su[32];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) a[k] = (lane < h && k < w) ? L[off + lane + int64_t(h) * k] : 0.0;
+        for (int k = 0; k < 32; ++k) {
+            const int v = (lane < h && k < w) ? qsu[k] : -2;
+            a[k] = (v <= -2) ? 0.0 : fma(al, qdy[k], qy[k]);   // padding starts from zero
+            su[k] = (v >= 0) ? v : ((v <= -3) ? -3 - v : -1);
+        }
+        if (b + 1 < nb) issue(b + 1);
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (su[k] >= 0) a[k] += U[su[k]];
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             if (k < w) {   // uniform
@@ -226,9 +253,11 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
             if (lane == 0) fail[cand] = b + 1;
             return;   // uniform
         }
+        if (keep) {
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
-            if (k < w && lane < h && lane >= k) L[off + lane + int64_t(h) * k] = a[k];
+            for (int k = 0; k < 32; ++k)
+                if (k < w && lane < h) L[off + lane + int64_t(h) * k] = (lane >= k) ? a[k] : 0.0;
+        }
         if (lane >= w && lane < h) {
 #pragma unroll
             for (int k = 0; k < 32; k += 2)
@@ -250,15 +279,17 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
             }
             return s0 + s1;
         };
+        auto apply = [&](int u, int pr) { U[u >> 1] = ((u & 1) ? 0.0 : U[u >> 1]) - dot_rows(pr); };
 #pragma unroll
-        for (int m = 0; m < kPrefetch; ++m)
-            if (ps[m] >= 0) L[ps[m]] = old[m] - dot_rows(pp[m]);
-        for (int t = 64 * kPrefetch + lane; t < np; t += 64) {
-            const int sl = up_slot[p0 + t];
-            if (sl >= 0) L[sl] -= dot_rows(up_pair[p0 + t]);
+        for (int m = 0; m < kPairsPer; ++m)
+            if (pu[m] >= 0) apply(pu[m], pp[m]);
+        for (int t = 64 * kPairsPer + lane; t < np; t += 64) {
+            const int u = up_u[p0 + t];
+            if (u >= 0) apply(u, up_pair[p0 + t]);
         }
-        // the next block's loads must see this block's stores (other lanes' included)
-        __threadfence_block();
+        // the next block reads these updates (other lanes' included)
+        if (POOL) __builtin_amdgcn_s_waitcnt(0xc07f);
+        else __threadfence_block();
         __builtin_amdgcn_wave_barrier();
     }
     if (lane == 0) fail[cand] = 0;
@@ -434,18 +465,28 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 
 }  // namespace
 
-int sn_init_grid(int64_t nslot) {
-    int64_t g = (nslot + 255) / 256;
-    return int(g < 1 ? 1 : (g > 256 ? 256 : g));
+// LDS of the one-wave factorisation: the rows of L21 plus, with a pool, the pool
+static size_t wave_chol_lds(const DevStruct &d) {
+    return sizeof(double) * (size_t(d.max_h) * 32 + (d.u_pool ? size_t(d.nU) : 0));
 }
 
-void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st) {
+static void launch_wave_chol(const DevStruct &d, int nc, const double *Y, const double *dY,
+                             const double *bracket, int round, int ntest, double gamma, double *L, int64_t stride,
+                             double *U, int *fail, hipStream_t st) {
+    const int prcap = d.max_h * 32;
+    if (d.u_pool)
+        hipLaunchKernelGGL(k_sn_chol_wave<true>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
+                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.slot_u, Y, dY, bracket, round, ntest,
+                           gamma, L, stride, U, d.nU, prcap, fail);
+    else
+        hipLaunchKernelGGL(k_sn_chol_wave<false>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
+                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.slot_u, Y, dY, bracket, round, ntest,
+                           gamma, L, stride, U, d.nU, prcap, fail);
+}
+
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, int *fail, hipStream_t st) {
     if (d.max_h <= 64) {
-        hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), 1), dim3(256), 0, st, d.nslot, d.wE, Y,
-                           (const double *)nullptr, (const double *)nullptr, 0, 1, 0.0, L, int64_t(0));
-        hipLaunchKernelGGL(k_sn_chol_wave, dim3(1), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st, d.nb,
-                           d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
-                           (const double *)nullptr, 0, L, int64_t(0), fail);
+        launch_wave_chol(d, 1, Y, nullptr, nullptr, 0, 1, 0.0, L, 0, U, fail, st);
         return;
     }
     const size_t lds = size_t(d.max_panel) * sizeof(double);
@@ -457,16 +498,12 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, h
 int dual_step_candidates(int round, const int *ntest) { return round == 0 ? ntest[0] + 1 : 2 * ntest[round]; }
 
 void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
-                      double gamma, double *cand, int *fail, double *bracket, hipStream_t st) {
+                      double gamma, double *cand, double *U, int *fail, double *bracket, hipStream_t st) {
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     for (int r = 0; r < rounds; ++r) {
         const int nc = dual_step_candidates(r, ntest);
         if (d.max_h <= 64) {
-            hipLaunchKernelGGL(k_cand_init, dim3(sn_init_grid(d.nslot), nc), dim3(256), 0, st, d.nslot, d.wE, Y,
-                               dY, (const double *)bracket, r, ntest[r], gamma, cand, d.nslot);
-            hipLaunchKernelGGL(k_sn_chol_wave, dim3(nc), dim3(64), size_t(d.max_h) * 32 * sizeof(double), st,
-                               d.nb, d.bl_first, d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot,
-                               (const double *)bracket, r, cand, d.nslot, fail);
+            launch_wave_chol(d, nc, Y, dY, bracket, r, ntest[r], gamma, cand, d.nslot, U, fail, st);
         } else {
             hipLaunchKernelGGL(k_sn_chol, dim3(nc), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
                                d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket,

@@ -48,6 +48,15 @@ struct DevStruct {
     const int64_t *up_ptr = nullptr;    // nb + 1: update pairs of each block
     const int *up_pair = nullptr;       // (a | c << 16), a >= c, indices into the non-own rows
     const int *up_slot = nullptr;       // target slot, -1 if not stored (value is exactly zero)
+    // pending updates of the one-wave factorisation live in slots: up_u = (slot << 1) |
+    // (first update of the slot in block order), or -1; slot_u = slot of an E slot that
+    // receives updates, -1 if none; on padding -2, or -3 - slot if it receives updates.  With u_pool the nU slots are a pool
+    // in LDS reused after their panel is consumed; otherwise one slot per target entry,
+    // in global memory, nU per candidate.
+    const int *up_u = nullptr;
+    const int *slot_u = nullptr;        // nslot
+    int64_t nU = 0;
+    int u_pool = 0;
     int nfwd = 0, nbwd = 0;
     const int *col_block = nullptr;     // n: block of every column
     const int *slot_row = nullptr;      // nslot: row position of an E slot, -1 on padding
@@ -108,15 +117,18 @@ void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, 
 void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
 
 // ---- factorisations (k_factor.hip)
-// Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block
-void launch_sn_chol(const DevStruct &d, const double *Y, double *L, int *fail, hipStream_t st);
+// Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block.  U: scratch of
+// d.nU doubles per candidate (kept pending updates); the dual step needs
+// dual_step_candidates(0, ntest) * d.nU of it.
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, int *fail, hipStream_t st);
 // largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of
 // parallel factorisations of ntest[r] test points (log grid, then even grids inside
 // the bracket) plus their gamma twins; the result is bracket[0] (a lower bound;
 // bracket[1] an upper bound), bracket[3] the candidate holding the factor of
-// Y + gamma bracket[0] dY (or -1), all on the device
+// Y + gamma bracket[0] dY (or -1), all on the device.  Only the gamma twins store
+// their factors (in cand, d.nslot doubles each); the other tests keep nothing.
 void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
-                      double gamma, double *cand, int *fail, double *bracket, hipStream_t st);
+                      double gamma, double *cand, double *U, int *fail, double *bracket, hipStream_t st);
 // candidates launched in a round (test points and their gamma twins)
 int dual_step_candidates(int round, const int *ntest);
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
