@@ -68,6 +68,7 @@ struct sdpc_handle {
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
     double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
+    double *ydw = nullptr, *ydw_dual = nullptr;   // row-major (Y, dY) tiles of the Y factor / dual step
     int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
                             // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
     int64_t ldb = 0;
@@ -326,8 +327,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             }
         }
         // the pool fits when the factorisation's LDS stays within 32 KB (four waves per CU)
-        const size_t pool_lds = sizeof(double) * (size_t(S.max_h) * 32 + size_t(used));
-        d.u_pool = (pool_lds <= 32 * 1024) ? 1 : 0;
+        d.u_pool = (wave_chol_lds_bytes(S.max_h, used) <= 32 * 1024) ? 1 : 0;
         if (!d.u_pool) {   // one slot per target entry, in global memory
             int k = 0;
             for (int64_t s = 0; s < S.nslot; ++s)
@@ -347,6 +347,21 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         // they receive updates (fill inside an amalgamated block)
         for (int64_t s = 0; s < S.nslot; ++s)
             if (!S.isE[s]) slot_u[s] = (slot_u[s] >= 0) ? -3 - slot_u[s] : -2;
+    }
+    // the same codes per 64 x 32 panel tile, row-major (the one-wave factorisation's
+    // read order), -2 outside the panel
+    std::vector<int> su_rows;
+    if (S.max_h <= 64 && S.max_w <= 32) {
+        su_rows.assign(size_t(S.nb) * 64 * 32, -2);
+        for (int b = 0; b < S.nb; ++b) {
+            const int w = S.bl_first[b + 1] - S.bl_first[b];
+            const int hh = int(S.bl_rptr[b + 1] - S.bl_rptr[b]);
+            for (int i = 0; i < hh; ++i)
+                for (int k = 0; k < w; ++k)
+                    su_rows[(size_t(b) * 64 + i) * 32 + k] = slot_u[S.bl_off[b] + i + int64_t(hh) * k];
+        }
+    } else {
+        su_rows.assign(1, -2);
     }
     // ---- cliques
     std::vector<int64_t> cl_ptr(S.ncl + 1, 0), cl_map_ptr(S.ncl + 1, 0);
@@ -529,6 +544,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.up_slot, up_slot));
     TRY(upload(h, &d.up_u, up_u));
     TRY(upload(h, &d.slot_u, slot_u));
+    TRY(upload(h, &d.su_rows, su_rows));
     TRY(upload(h, &d.col_block, S.col_block));
     TRY(upload(h, &d.slot_row, slot_row));
     TRY(upload(h, &d.slot_col, slot_col));
@@ -593,6 +609,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
     TRY(dalloc(h, &h->ubuf, std::max<size_t>(size_t(d.nU), 1) * kCand));
+    TRY(dalloc(h, &h->ydw, wave_chol_work_doubles(d)));
+    TRY(dalloc(h, &h->ydw_dual, wave_chol_work_doubles(d)));
     TRY(dalloc(h, &h->part, std::max(size_t(2) * dX_chunks(d) * ns, size_t(rhs_had_parts(d)) * n)));
     TRY(dalloc(h, &h->flags, kCand + 8));
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
@@ -737,7 +755,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
         HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
                                  size_t(d.nslot) * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
-        launch_sn_chol(d, Y, h->N, h->ubuf, h->flags + kCand + 5, st);
+        launch_sn_chol(d, Y, h->N, h->ubuf, h->ydw, h->flags + kCand + 5, st);
     h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
     HIPCHK(h, hipEventRecord(h->evs[1], st));
@@ -776,8 +794,8 @@ double since(std::chrono::steady_clock::time_point t0) {
 sdpc_status dual_step_launch(sdpc_handle *h) {
     HIPCHK(h, hipEventRecord(h->ev_dy, h->st));
     HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_dy, 0));
-    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->ubuf, h->flags,
-                     h->alphas, h->side);
+    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->ubuf, h->ydw_dual,
+                     h->flags, h->alphas, h->side);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipEventRecord(h->ev_dual, h->side));
     return SDPC_OK;

@@ -150,59 +150,85 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
     if (tid == 0) fail[cand] = 0;
 }
 
+// (Y, dY) of every storage block as a 64 x 32 row-major tile of pairs (zeros
+// outside the panel; dY == nullptr gives dy = 0), the layout in which the one-wave
+// factorisation reads a panel row per lane with 16-byte loads.
+__global__ void __launch_bounds__(256)
+k_yd_rows(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
+          const double *__restrict__ Y, const double *__restrict__ dY, double2 *__restrict__ yd) {
+    const int b = blockIdx.x;
+    const int w = bl_first[b + 1] - bl_first[b];
+    const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
+    const int64_t off = bl_off[b];
+    for (int e = threadIdx.x; e < 64 * 32; e += blockDim.x) {
+        const int i = e / 32, k = e % 32;
+        double2 v = double2{0.0, 0.0};
+        if (i < h && k < w) {
+            const int64_t s = off + i + int64_t(h) * k;
+            v = double2{Y[s], dY ? dY[s] : 0.0};
+        }
+        yd[size_t(b) * 64 * 32 + e] = v;
+    }
+}
+
 // Y = N N^T on the storage blocks by a single wave (panels of at most 64 rows and
 // 32 columns).  Lane i holds row i of the panel in registers; the pivot and the
 // scaled pivot column reach the other lanes through readlane, so the elimination
 // needs neither LDS nor barriers.  The update of the ancestors, N(U, U) -=
 // L21 L21^T, takes its operands from LDS (rows of L21, row-major).
-// blockIdx.x selects the candidate Y + alpha_c dY (dY == nullptr: Y itself).  The
+// blockIdx.x selects the candidate Y + alpha_c dY (dual == false: Y itself).  The
 // candidate is never written out: a panel is formed when its block is reached,
-// from Y and dY (read one block ahead, while the previous block is factorised)
-// and the pending updates of its descendants.  Those live in slots (slot_u maps
+// from Y and dY (copied per panel row-major by k_yd_rows, read one block ahead
+// while the previous block is factorised) and the pending updates of its
+// descendants.  Those live in slots (slot_u maps
 // a storage slot to its slot: -1 if it receives no update; on padding, which
 // starts from zero, -2 or -3 - slot); with POOL
 // the slots are a pool in LDS, reused once a panel has consumed them, otherwise
 // a per-candidate array in global memory.  The first update of a slot in block
 // order overwrites it (up_u = slot << 1 | first), so no slot needs clearing.  The
 // factor is stored (the whole panel, zeros above the diagonal) only by the
-// candidates whose factor is used afterwards: the gamma twins, or every
-// candidate when dY is null.
+// candidates whose factor is used afterwards: the gamma twins, or the single
+// factorisation when dual is false.
 constexpr int kPairsPer = 4;   // update pairs per lane loaded ahead of the elimination
+constexpr int kPrLd = 34;      // LDS row stride of L21 (doubles): rows fall on different banks
 
 template <bool POOL>
 __global__ void __launch_bounds__(64)
 k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
                const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
-               const int *__restrict__ up_pair, const int *__restrict__ up_u, const int *__restrict__ slot_u,
-               const double *__restrict__ Y, const double *__restrict__ dY, const double *__restrict__ bracket,
-               int round, int ntest, double gamma, double *__restrict__ Lbase, int64_t stride,
-               double *__restrict__ Ubase, int64_t ustride, int prcap, int *__restrict__ fail) {
+               const int *__restrict__ up_pair, const int *__restrict__ up_u, const int *__restrict__ su_rows,
+               const double2 *__restrict__ yd_rows, bool dual, const double *__restrict__ bracket, int round,
+               int ntest, double gamma, double *__restrict__ Lbase, int64_t stride, double *__restrict__ Ubase,
+               int64_t ustride, int prcap, int *__restrict__ fail) {
     extern __shared__ double sm[];
-    double *Pr = sm;   // rows >= w of the factored panel, 32 doubles per row (prcap doubles)
+    double *Pr = sm;   // rows >= w of the factored panel, kPrLd doubles per row (prcap doubles)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
-    if (dY && round > 0 && bracket[2] != 0.0) {   // settled: nothing to test
+    if (dual && round > 0 && bracket[2] != 0.0) {   // settled: nothing to test
         if (lane == 0) fail[cand] = 0;
         return;
     }
-    const double al = dY ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
-    const bool keep = !dY || cand >= ntest;   // the factor is used afterwards
+    const double al = dual ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
+    const bool keep = !dual || cand >= ntest;   // the factor is used afterwards
     double *L = Lbase + cand * stride;
     double *U = POOL ? sm + prcap : Ubase + cand * ustride;
-    // inputs of the next block, in flight while the current one is processed
-    // (clamped indices: every load is in bounds, the selects come later)
-    double qy[32], qdy[32];
+    // inputs of the next block (row lane of its 64 x 32 tile, row-major: 32 (y, dy)
+    // pairs and 32 slot codes, forty 16-byte loads), in flight while the current
+    // block is processed
+    double2 q[32];
     int qsu[32];
     auto issue = [&](int bb) {
-        const int ww = bl_first[bb + 1] - bl_first[bb];
-        const int hh = int(bl_rptr[bb + 1] - bl_rptr[bb]);
-        const int64_t oo = bl_off[bb] + min(lane, hh - 1);
+        const size_t r = (size_t(bb) * 64 + lane) * 32;
+        const int4 *sp = reinterpret_cast<const int4 *>(su_rows + r);
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            const int64_t sk = oo + int64_t(hh) * min(k, ww - 1);
-            qsu[k] = slot_u[sk];
-            qy[k] = Y[sk];
-            qdy[k] = dY ? dY[sk] : 0.0;
+        for (int k = 0; k < 32; ++k) q[k] = yd_rows[r + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int4 t = sp[u];
+            qsu[4 * u] = t.x;
+            qsu[4 * u + 1] = t.y;
+            qsu[4 * u + 2] = t.z;
+            qsu[4 * u + 3] = t.w;
         }
     };
     issue(0);
@@ -225,8 +251,8 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
         int su[32];
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
-            const int v = (lane < h && k < w) ? qsu[k] : -2;
-            a[k] = (v <= -2) ? 0.0 : fma(al, qdy[k], qy[k]);   // padding starts from zero
+            const int v = qsu[k];   // -2 outside the panel as well
+            a[k] = (v <= -2) ? 0.0 : fma(al, q[k].y, q[k].x);   // padding starts from zero
             su[k] = (v >= 0) ? v : ((v <= -3) ? -3 - v : -1);
         }
         if (b + 1 < nb) issue(b + 1);
@@ -261,15 +287,15 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
         if (lane >= w && lane < h) {
 #pragma unroll
             for (int k = 0; k < 32; k += 2)
-                *reinterpret_cast<double2 *>(Pr + (lane - w) * 32 + k) =
+                *reinterpret_cast<double2 *>(Pr + (lane - w) * kPrLd + k) =
                     double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
         }
         // one wave: its own LDS stores only need to have completed, no barrier
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
         auto dot_rows = [&](int pr) {
-            const double2 *x = reinterpret_cast<const double2 *>(Pr + (pr & 0xffff) * 32);
-            const double2 *y = reinterpret_cast<const double2 *>(Pr + (pr >> 16) * 32);
+            const double2 *x = reinterpret_cast<const double2 *>(Pr + (pr & 0xffff) * kPrLd);
+            const double2 *y = reinterpret_cast<const double2 *>(Pr + (pr >> 16) * kPrLd);
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -467,26 +493,36 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 
 // LDS of the one-wave factorisation: the rows of L21 plus, with a pool, the pool
 static size_t wave_chol_lds(const DevStruct &d) {
-    return sizeof(double) * (size_t(d.max_h) * 32 + (d.u_pool ? size_t(d.nU) : 0));
+    return sizeof(double) * (size_t(d.max_h) * kPrLd + (d.u_pool ? size_t(d.nU) : 0));
 }
 
-static void launch_wave_chol(const DevStruct &d, int nc, const double *Y, const double *dY,
-                             const double *bracket, int round, int ntest, double gamma, double *L, int64_t stride,
-                             double *U, int *fail, hipStream_t st) {
-    const int prcap = d.max_h * 32;
+static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool dual, const double *bracket,
+                             int round, int ntest, double gamma, double *L, int64_t stride, double *U, int *fail,
+                             hipStream_t st) {
+    const int prcap = d.max_h * kPrLd;
     if (d.u_pool)
         hipLaunchKernelGGL(k_sn_chol_wave<true>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
-                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.slot_u, Y, dY, bracket, round, ntest,
-                           gamma, L, stride, U, d.nU, prcap, fail);
+                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.su_rows, yd, dual, bracket, round,
+                           ntest, gamma, L, stride, U, d.nU, prcap, fail);
     else
         hipLaunchKernelGGL(k_sn_chol_wave<false>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
-                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.slot_u, Y, dY, bracket, round, ntest,
-                           gamma, L, stride, U, d.nU, prcap, fail);
+                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.su_rows, yd, dual, bracket, round,
+                           ntest, gamma, L, stride, U, d.nU, prcap, fail);
 }
 
-void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, int *fail, hipStream_t st) {
+size_t wave_chol_work_doubles(const DevStruct &d) { return size_t(d.nb) * 64 * 32 * 2; }
+
+size_t wave_chol_lds_bytes(int max_h, int64_t npool) {
+    return sizeof(double) * (size_t(max_h) * kPrLd + size_t(npool));
+}
+
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,
+                    hipStream_t st) {
     if (d.max_h <= 64) {
-        launch_wave_chol(d, 1, Y, nullptr, nullptr, 0, 1, 0.0, L, 0, U, fail, st);
+        double2 *yd = reinterpret_cast<double2 *>(work);
+        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, Y,
+                           (const double *)nullptr, yd);
+        launch_wave_chol(d, 1, yd, false, nullptr, 0, 1, 0.0, L, 0, U, fail, st);
         return;
     }
     const size_t lds = size_t(d.max_panel) * sizeof(double);
@@ -498,12 +534,16 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, i
 int dual_step_candidates(int round, const int *ntest) { return round == 0 ? ntest[0] + 1 : 2 * ntest[round]; }
 
 void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
-                      double gamma, double *cand, double *U, int *fail, double *bracket, hipStream_t st) {
+                      double gamma, double *cand, double *U, double *work, int *fail, double *bracket,
+                      hipStream_t st) {
     const size_t lds = size_t(d.max_panel) * sizeof(double);
+    double2 *yd = reinterpret_cast<double2 *>(work);
+    if (d.max_h <= 64)
+        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, Y, dY, yd);
     for (int r = 0; r < rounds; ++r) {
         const int nc = dual_step_candidates(r, ntest);
         if (d.max_h <= 64) {
-            launch_wave_chol(d, nc, Y, dY, bracket, r, ntest[r], gamma, cand, d.nslot, U, fail, st);
+            launch_wave_chol(d, nc, yd, true, bracket, r, ntest[r], gamma, cand, d.nslot, U, fail, st);
         } else {
             hipLaunchKernelGGL(k_sn_chol, dim3(nc), dim3(kCholThreads), lds, st, d.nb, d.nslot, d.wE, d.bl_first,
                                d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket,

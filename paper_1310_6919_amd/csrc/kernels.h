@@ -57,6 +57,7 @@ struct DevStruct {
     const int *slot_u = nullptr;        // nslot
     int64_t nU = 0;
     int u_pool = 0;
+    const int *su_rows = nullptr;       // nb x 64 x 32: slot_u of each panel tile, row-major (-2 outside)
     int nfwd = 0, nbwd = 0;
     const int *col_block = nullptr;     // n: block of every column
     const int *slot_row = nullptr;      // nslot: row position of an E slot, -1 on padding
@@ -118,9 +119,14 @@ void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
 
 // ---- factorisations (k_factor.hip)
 // Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block.  U: scratch of
-// d.nU doubles per candidate (kept pending updates); the dual step needs
-// dual_step_candidates(0, ntest) * d.nU of it.
-void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, int *fail, hipStream_t st);
+// d.nU doubles per candidate (pending updates, when they are not kept in LDS); the
+// dual step needs dual_step_candidates(0, ntest) * d.nU of it.
+void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,
+                    hipStream_t st);
+// work (doubles) of launch_sn_chol and launch_dual_step; LDS of their one-wave
+// factorisation with a pool of npool update slots
+size_t wave_chol_work_doubles(const DevStruct &d);
+size_t wave_chol_lds_bytes(int max_h, int64_t npool);
 // largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of
 // parallel factorisations of ntest[r] test points (log grid, then even grids inside
 // the bracket) plus their gamma twins; the result is bracket[0] (a lower bound;
@@ -128,7 +134,8 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, i
 // Y + gamma bracket[0] dY (or -1), all on the device.  Only the gamma twins store
 // their factors (in cand, d.nslot doubles each); the other tests keep nothing.
 void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
-                      double gamma, double *cand, double *U, int *fail, double *bracket, hipStream_t st);
+                      double gamma, double *cand, double *U, double *work, int *fail, double *bracket,
+                      hipStream_t st);
 // candidates launched in a round (test points and their gamma twins)
 int dual_step_candidates(int round, const int *ntest);
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
