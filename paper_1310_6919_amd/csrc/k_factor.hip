@@ -256,9 +256,13 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
             su[k] = (v >= 0) ? v : ((v <= -3) ? -3 - v : -1);
         }
         if (b + 1 < nb) issue(b + 1);
+        // every lane reads a slot (slot 0 where there is none) and discards the unused
+        // values: no divergent branches, all reads in flight together
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
-            if (su[k] >= 0) a[k] += U[su[k]];
+        for (int k = 0; k < 32; ++k) {
+            const double pv = U[max(su[k], 0)];
+            a[k] += (su[k] >= 0) ? pv : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
             if (k < w) {   // uniform
@@ -493,7 +497,7 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 
 // LDS of the one-wave factorisation: the rows of L21 plus, with a pool, the pool
 static size_t wave_chol_lds(const DevStruct &d) {
-    return sizeof(double) * (size_t(d.max_h) * kPrLd + (d.u_pool ? size_t(d.nU) : 0));
+    return sizeof(double) * (size_t(d.max_h) * kPrLd + (d.u_pool ? size_t(d.nU < 1 ? 1 : d.nU) : 0));
 }
 
 static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool dual, const double *bracket,
@@ -513,7 +517,7 @@ static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool
 size_t wave_chol_work_doubles(const DevStruct &d) { return size_t(d.nb) * 64 * 32 * 2; }
 
 size_t wave_chol_lds_bytes(int max_h, int64_t npool) {
-    return sizeof(double) * (size_t(max_h) * kPrLd + size_t(npool));
+    return sizeof(double) * (size_t(max_h) * kPrLd + size_t(npool < 1 ? 1 : npool));
 }
 
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,
