@@ -78,8 +78,8 @@ struct sdpc_handle {
     hipEvent_t evs[6]{};   // phases of the SCM evaluation
     hipStream_t side = nullptr;   // second stream (default priority): dual step alongside dX and alpha_p
     hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
-    int *pflags_f = nullptr, *pflags_b = nullptr;   // hand-over flags of the SCM Cholesky and the SCE solve
-    double *pwork = nullptr;                          // the SCM Cholesky's diagonal-block inverse
+    int *pflags_b = nullptr;   // hand-over flags of the SCE backward solve
+    double *pwork = nullptr;   // diagonal factors of the SCM Cholesky waiting for the next launch
     int epoch = 0;                                    // last epoch used on those flags
     int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
     bool xside_ready = false;   // Lhat, its diagonal inverses and X^ already belong to the current X
@@ -601,9 +601,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->W, nn));
     TRY(dalloc(h, &h->T, std::max<size_t>(size_t(d.nS), 1)));
     TRY(dalloc(h, &h->B, size_t(h->ldb) * std::max(m, 1)));
-    TRY(dalloc(h, &h->pflags_f, size_t(potrf_flag_count(m))));
-    TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->pflags_b, size_t(potrf_flag_count(m))));
+    TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->scal, 16));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
@@ -616,7 +615,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), h->st));
-    HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flag_count(m) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
     for (auto &e : h->evs) HIPCHK(h, hipEventCreate(&e));
@@ -726,7 +724,7 @@ sdpc_status check_flags(sdpc_handle *h, bool potrf) {
         return fail(h, SDPC_E_NOT_PD, "clique block of the updated Xbar not positive definite (clique " +
                                           std::to_string(fl[kCand + 3] - 1) + ")");
     if (fl[kCand] || fl[kCand + 4]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
-    if (potrf && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCM Cholesky / SCE solve: an internal hand-over wait ran out");
+    if (potrf && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCE solve: an internal hand-over wait ran out");
     if (potrf && fl[kCand + 2])
         return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
     return SDPC_OK;
@@ -775,7 +773,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
     HIPCHK(h, hipEventRecord(h->evs[4], st));
-    if (factor) launch_potrf(d.m, B, ldb, h->pwork, h->pflags_f, ++h->epoch, h->flags + kCand + 2, st);
+    if (factor) launch_potrf(d.m, B, ldb, h->pwork, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(h->evs[5], st));
     HIPCHK(h, hipGetLastError());
     if (in_step) return SDPC_OK;
@@ -865,7 +863,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipEventRecord(ev[1], st));
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
     launch_set_row(d.m, h->g, h->B + d.m, h->ldb, st);
-    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pwork, h->pflags_f, ++h->epoch, h->flags + kCand + 2, st);
+    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[6], st));
     launch_potrs_bwd(d.m, h->B, h->ldb, h->B + d.m, h->ldb, h->dz, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[2], st));
@@ -991,7 +989,7 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m) {
     if (!h || !d_B || m < 0 || ldb < m || m > h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_potrf arguments") : SDPC_E_ARG;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), h->st));
-    launch_potrf(m, d_B, ldb, h->pwork, h->pflags_f, ++h->epoch, h->flags + kCand + 2, h->st);
+    launch_potrf(m, d_B, ldb, h->pwork, h->flags + kCand + 2, h->st);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(h->st));
     const int f = read_flag(h, kCand + 2);

@@ -2,25 +2,29 @@
 // Section 3.1), and the backward substitution of the SCE (eq. SCE).
 //
 // Right-looking, 64-wide column blocks, one fused launch per block column s:
-//   workgroup 0          applies the pending panel s-1 to the diagonal tile and
-//                        factorises it in one wave (lane = row, pivot column
-//                        broadcast with readlane), then releases flags[s];
-//   workgroups 1..nt-1   apply panel s-1 to their tile of column block s, wait
-//                        for flags[s] and solve X R_ss^T = C by forward
-//                        substitution (lane = row of the tile);
+//   workgroups 0..nt-1   tile rows s .. of column block s.  Each applies the
+//                        pending panel s-1 to the diagonal tile and factorises it
+//                        in one wave (lane = row, pivot column broadcast with
+//                        readlane).  Workgroup 0 stores R_ss and reports a failed
+//                        pivot; every other one also applies panel s-1 to its own
+//                        tile, forms R_ss^{-1} (block inverses, the off-diagonal
+//                        block on the MFMA) and solves X R_ss^T = C as one MFMA
+//                        product.  Repeating the small factorisation in every
+//                        workgroup of the column spares a hand-over through
+//                        memory on the critical path.
 //   the others           apply panel s-1 to every lower tile of the column blocks
 //                        s+1 .. (the bulk of the trailing update), overlapping the
-//                        diagonal factorisation of the same launch.
+//                        diagonal factorisations of the same launch.
 // So column block s+1 only lacks panel s when launch s+1 starts, and the launch
 // boundary is the only grid-wide synchronisation.  Rows beyond m ride along:
 // with the right-hand side g stored as row m, the sweep leaves R^{-1} g there
 // (the forward substitution of the SCE), and only R^T x = R^{-1} g remains,
 // done by one launch whose workgroups hand the blocks of x down through flags.
 //
-// Every wait is a bounded spin on a flag released by a workgroup with a lower
-// index (dispatched earlier), so it cannot deadlock; a wait that runs out marks
-// the call failed (fail = -1) instead of hanging.  Flags hold the epoch of the
-// call that released them, so they never need to be cleared.
+// Every wait of that solve is a bounded spin on a flag released by a workgroup
+// with a lower index (dispatched earlier), so it cannot deadlock; a wait that
+// runs out marks the call failed (fail = -1) instead of hanging.  Flags hold the
+// epoch of the call that released them, so they never need to be cleared.
 #include "chol_reg.h"
 #include "kernels.h"
 
@@ -162,13 +166,30 @@ __device__ inline void potrf64_wave(double (&lo)[32], double (&hi)[32], double *
     panel32_wave<32>(hi);
 }
 
+// The factor of diagonal block s (parked column-major in Rscr[s & 1]) into B:
+// rows J0 + i < rows (right-hand-side rows riding along included), columns
+// k < jb, k <= i.
+__device__ inline void put_diag(double *B, int64_t ldb, int rows, int m, int s, const double *Rscr) {
+    const int J0 = NB * s;
+    const int jb = (m - J0 < NB) ? (m - J0) : NB;
+    const double *Rs = Rscr + (s & 1) * NB * NB;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+        const int i = idx % NB, k = idx / NB;
+        if (J0 + i < rows && k < jb && k <= i) B[(J0 + i) + ldb * (J0 + k)] = Rs[idx];
+    }
+}
+
 __global__ void __launch_bounds__(256)
-k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__restrict__ flags, int epoch,
-            int *__restrict__ fail, double *__restrict__ Rinv) {
+k_put_diag(double *__restrict__ B, int64_t ldb, int rows, int m, int s, const double *__restrict__ Rscr) {
+    put_diag(B, ldb, rows, m, s, Rscr);
+}
+
+__global__ void __launch_bounds__(256)
+k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__restrict__ fail,
+            double *__restrict__ Rscr) {
     __shared__ double S[NB * LDS_LD];   // the updated tile, row-major; then the diagonal factor
     __shared__ double Ai[32 * 33], Ci[32 * 33], Eb[32 * 33];   // blocks of the factor's inverse
     __shared__ double invd[NB];
-    __shared__ int go;
     const int tid = threadIdx.x;
     const TileIdx t;
     const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
@@ -209,24 +230,27 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
                 }
         return;
     }
-    // column block s: tile row I, with panel s-1 applied
+    // column block s, tile row I.  Every workgroup of the column block factorises the
+    // diagonal tile R_ss itself: a panel tile needs R_ss^{-1}, which it then forms in
+    // its own LDS, so no workgroup waits on another; the diagonal workgroup alone
+    // reports a failed pivot and stores R_ss.
     const int I = s + int(blockIdx.x), I0 = NB * I;
     const bool diag = (I == s);
-    {
-        double c[2][2][4];
+    // a tile of column block s with panel s-1 applied, in the accumulator layout
+    auto stage = [&](int R0, bool lower, double (&c)[2][2][4]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gi = I0 + t.row(a), gk = t.col(b, r);
-                    c[a][b][r] = (gi < rows && gk < jb && (!diag || gi >= J0 + gk)) ? B[gi + ldb * (J0 + gk)] : 0.0;
+                    const int gi = R0 + t.row(a), gk = t.col(b, r);
+                    c[a][b][r] = (gi < rows && gk < jb && (!lower || gi >= J0 + gk)) ? B[gi + ldb * (J0 + gk)] : 0.0;
                 }
         if (s >= 1) {
             d4 acc[2][2];
             zero_acc(acc);
-            tile_mma(t, B, ldb, I0, rows, J0 - NB, B, ldb, J0, m, J0 - NB, NB, acc);
+            tile_mma(t, B, ldb, R0, rows, J0 - NB, B, ldb, J0, m, J0 - NB, NB, acc);
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -234,42 +258,74 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
 #pragma unroll
                     for (int r = 0; r < 4; ++r) c[a][b][r] -= acc[a][b][r];
         }
+    };
+    auto to_lds = [&](const double (&c)[2][2][4]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) S[t.row(a) * LDS_LD + t.col(b, r)] = c[a][b][r];
+    };
+    // the updated panel tile (I, s) is parked in its own place in B while the diagonal
+    // tile is factorised (registers are short there); each thread reads back exactly
+    // the entries it wrote
+    auto own_rw = [&](double (&c)[2][2][4], bool put) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = I0 + t.row(a), gk = t.col(b, r);
+                    const bool in = gi < rows && gk < jb;
+                    if (put) {
+                        if (in) B[gi + ldb * (J0 + gk)] = c[a][b][r];
+                    } else {
+                        c[a][b][r] = in ? B[gi + ldb * (J0 + gk)] : 0.0;
+                    }
+                }
+    };
+    {
+        double cd[2][2][4];
+        stage(J0, true, cd);
+        if (!diag) {
+            double co[2][2][4];
+            stage(I0, false, co);
+            own_rw(co, true);
+        }
+        to_lds(cd);
     }
     __syncthreads();
-    if (diag) {
-        if (tid < 64) {
-            __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
-            // rows of the tile below the block's own jb rows (right-hand-side rows riding
-            // along the last block) keep their values in the jb active columns: the
-            // elimination then performs their forward substitution
-            const int lane = tid;
-            const bool real = J0 + lane < rows;
-            double lo[32], hi[32];
+    if (tid < 64) {
+        __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
+        // rows of the tile below the block's own jb rows (right-hand-side rows riding
+        // along the last block) keep their values in the jb active columns: the
+        // elimination then performs their forward substitution
+        const int lane = tid;
+        const bool real = J0 + lane < rows;
+        double lo[32], hi[32];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {   // every load is in bounds; selects afterwards
-                const double v0 = S[lane * LDS_LD + k], v1 = S[lane * LDS_LD + 32 + k];
-                const int k2 = 32 + k;
-                lo[k] = (real && k < jb) ? (k <= lane ? v0 : 0.0) : (lane == k ? 1.0 : 0.0);
-                hi[k] = (real && k2 < jb) ? (k2 <= lane ? v1 : 0.0) : (lane == k2 ? 1.0 : 0.0);
-            }
-            __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile is in registers before S is reused
-            potrf64_wave(lo, hi, S);               // S serves as its scratch
+        for (int k = 0; k < 32; ++k) {   // every load is in bounds; selects afterwards
+            const double v0 = S[lane * LDS_LD + k], v1 = S[lane * LDS_LD + 32 + k];
+            const int k2 = 32 + k;
+            lo[k] = (real && k < jb) ? (k <= lane ? v0 : 0.0) : (lane == k ? 1.0 : 0.0);
+            hi[k] = (real && k2 < jb) ? (k2 <= lane ? v1 : 0.0) : (lane == k2 ? 1.0 : 0.0);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile is in registers before S is reused
+        potrf64_wave(lo, hi, S);               // S serves as its scratch
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                S[lane * LDS_LD + k] = lo[k];
-                S[lane * LDS_LD + 32 + k] = hi[k];
-            }
-            __builtin_amdgcn_s_waitcnt(0xc07f);
+        for (int k = 0; k < 32; ++k) {
+            S[lane * LDS_LD + k] = lo[k];
+            S[lane * LDS_LD + 32 + k] = hi[k];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        const double dg = S[lane * LDS_LD + lane];
+        if (diag) {
             // every pivot of the block must have been positive and finite
-            const double dg = S[lane * LDS_LD + lane];
             const unsigned long long badm = __ballot(lane < jb && !((dg > 0.0) && isfinite(dg)));
             if (badm != 0ull && lane == 0) atomicCAS(fail, 0, J0 + __ffsll((long long)badm));
+        } else {
             invd[lane] = 1.0 / dg;
             __builtin_amdgcn_s_waitcnt(0xc07f);
             // inverses of the diagonal blocks A = R(0:32, 0:32) (lanes 0..31) and
@@ -289,86 +345,82 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
             double *Xo = hb ? Ci : Ai;
 #pragma unroll
             for (int i = 0; i < 32; ++i) Xo[i * 33 + j] = x[i];
-            __builtin_amdgcn_s_setprio(0);
         }
-        __syncthreads();
-        // R^{-1}(32:64, 0:32) = -C^{-1} (R(32:64, 0:32) A^{-1}): two 32 x 32 x 32 products on
-        // the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2)
-        {
-            const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-            const int bi = wv >> 1, bj = wv & 1;
-            const bool rowok = 32 + 16 * bi + li < jb;
-            d4 e = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const int k = 4 * ks + lk;
-                const double xa = rowok ? S[(32 + 16 * bi + li) * LDS_LD + k] : 0.0;
-                const double za = Ai[k * 33 + 16 * bj + li];
-                e = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, e, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = e[r];
-            __syncthreads();
-            d4 f = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const int k = 4 * ks + lk;
-                const double xa = Ci[(16 * bi + li) * 33 + k];
-                const double za = Eb[k * 33 + 16 * bj + li];
-                f = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, f, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Rinv[(32 + 16 * bi + 4 * r + lk) + NB * (16 * bj + li)] = -f[r];
-        }
-        // the diagonal blocks and the zero block, column-major 64 x 64
-        for (int o = tid; o < NB * NB; o += blockDim.x) {
-            const int i = o % NB, k = o / NB;   // consecutive threads, consecutive rows
-            if (i >= 32 && k < 32) continue;    // formed above
-            double v;
-            if (i < 32) v = (k < 32) ? Ai[i * 33 + k] : 0.0;
-            else v = Ci[(i - 32) * 33 + (k - 32)];
-            Rinv[i + NB * k] = v;
-        }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) flag_release(&flags[s], epoch);
-        // the factor itself back into B (off the chain: the panel tiles only need R^{-1})
-        for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-            const int i = idx % NB, k = idx / NB;
-            if (J0 + i < rows && k < jb && k <= i) B[(J0 + i) + ldb * (J0 + k)] = S[i * LDS_LD + k];
-        }
-        return;
-    }
-    // panel tile: wait for R_ss^{-1} of this launch, then X = C R_ss^{-T} on the MFMA
-    // (C row-major in S; R^{-1} column-major in global memory)
-    if (tid == 0) {
-        const bool ok = flag_wait(&flags[s], epoch);
-        if (!ok) atomicCAS(fail, 0, -1);
-        go = ok && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
-    if (!go) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (diag) {
+        // R_ss goes to B one launch later: the other workgroups of this launch still
+        // read the diagonal tile.  It waits in Rscr[s & 1]; R_{s-1,s-1} moves to B now.
+        double *Rs = Rscr + (s & 1) * NB * NB;
+        for (int idx = tid; idx < NB * NB; idx += blockDim.x) Rs[idx] = S[(idx % NB) * LDS_LD + idx / NB];
+        if (s >= 1) put_diag(B, ldb, rows, m, s - 1, Rscr);
+        return;
+    }
+    // R^{-1}(32:64, 0:32) = F = -C^{-1} (R(32:64, 0:32) A^{-1}): two 32 x 32 x 32 products
+    // on the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2); F replaces
+    // the intermediate in Eb, the panel tile replaces R_ss in S
+    {
+        const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+        const int bi = wv >> 1, bj = wv & 1;
+        const bool rowok = 32 + 16 * bi + li < jb;
+        d4 e = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int k = 4 * ks + lk;
+            const double xa = rowok ? S[(32 + 16 * bi + li) * LDS_LD + k] : 0.0;
+            const double za = Ai[k * 33 + 16 * bj + li];
+            e = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, e, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = e[r];
+        __syncthreads();
+        double co[2][2][4];
+        own_rw(co, false);   // in flight during the second product
+        d4 f = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int k = 4 * ks + lk;
+            const double xa = Ci[(16 * bi + li) * 33 + k];
+            const double za = Eb[k * 33 + 16 * bj + li];
+            f = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, f, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = -f[r];
+        to_lds(co);
+    }
+    __syncthreads();
+    // X = C R_ss^{-T}: R^{-1}(col, k) is A^{-1} (col, k < 32), zero (col < 32 <= k),
+    // F (col >= 32, k < 32) or C^{-1} (col, k >= 32); columns < 32 need k < 32 only
     d4 acc[2][2];
     zero_acc(acc);
     {
+        const int nks = (t.qc == 0) ? 8 : 16;   // uniform per wave
         double a[2][16], b[2][16];
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
             const int k = 4 * ks + t.lk;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                a[u][ks] = S[(t.qr + 16 * u + t.li) * LDS_LD + k];   // C(row, k)
-                b[u][ks] = Rinv[(t.qc + 16 * u + t.li) + NB * k];     // R^{-1}(col, k)
+                const int col = 16 * u + t.li;   // within the wave's 32 columns
+                a[u][ks] = S[(t.qr + 16 * u + t.li) * LDS_LD + k];
+                double rv;
+                if (t.qc == 0) rv = (k < 32) ? Ai[col * 33 + k] : 0.0;
+                else rv = (k < 32) ? Eb[col * 33 + k] : Ci[col * 33 + (k - 32)];
+                b[u][ks] = rv;
             }
         }
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks)
+            if (ks < nks) {
 #pragma unroll
-            for (int ti = 0; ti < 2; ++ti)
+                for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < 2; ++tj)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[tj][ks], a[ti][ks], acc[ti][tj], 0, 0, 0);
+                    for (int tj = 0; tj < 2; ++tj)
+                        acc[ti][tj] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(b[tj][ks], a[ti][ks], acc[ti][tj], 0, 0, 0);
+            }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -455,23 +507,23 @@ __global__ void k_scatter_strided(int m, const double *__restrict__ a, double *_
 
 int potrf_flag_count(int m) { return (m + NB - 1) / NB + 1; }
 
-size_t potrf_work_doubles(int /*m*/) { return size_t(NB) * NB; }
+size_t potrf_work_doubles(int /*m*/) { return size_t(2) * NB * NB; }
 
-void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail,
-                       hipStream_t st) {
+void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *fail, hipStream_t st) {
     const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
     for (int s = 0; s < T_cols; ++s) {
         const int nt = T_rows - s;
         int nbulk = 0;
         if (s >= 1)
             for (int K = s + 1; K < T_cols; ++K) nbulk += T_rows - K;
-        hipLaunchKernelGGL(k_chol_step, dim3(nt + nbulk), dim3(256), 0, st, B, ldb, m, rows, s, flags, epoch, fail,
-                           work);
+        hipLaunchKernelGGL(k_chol_step, dim3(nt + nbulk), dim3(256), 0, st, B, ldb, m, rows, s, fail, work);
     }
+    if (T_cols > 0)
+        hipLaunchKernelGGL(k_put_diag, dim3(1), dim3(256), 0, st, B, ldb, rows, m, T_cols - 1, (const double *)work);
 }
 
-void launch_potrf(int m, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail, hipStream_t st) {
-    launch_potrf_rows(m, m, B, ldb, work, flags, epoch, fail, st);
+void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st) {
+    launch_potrf_rows(m, m, B, ldb, work, fail, st);
 }
 
 void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *u, int64_t ustride, double *x, int *flags,

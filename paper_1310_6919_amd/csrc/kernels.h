@@ -184,16 +184,16 @@ void launch_dense_times_agg(const DevStruct &d, const double *Xh, const double *
 
 // ---- dense FP64 Cholesky and SCE solve (k_dense.hip)
 // Dense Cholesky of B (lower, column-major, leading dimension ldb); rows m..rows-1
-// ride along (a right-hand side stored as row m ends as R^{-1} g).  flags holds
-// potrf_flag_count(m) ints, zero-initialised once; epoch must differ from every
-// earlier call's on the same flags.  fail gets pivot + 1 if B is not positive
-// definite, -1 if an internal wait ran out.
-// work holds potrf_work_doubles(m) doubles (the inverse of the current diagonal block).
+// ride along (a right-hand side stored as row m ends as R^{-1} g).  fail gets
+// pivot + 1 if B is not positive definite.  work: potrf_work_doubles(m) doubles.
+//
+// The backward solve's flags hold potrf_flag_count(m) ints, zero-initialised
+// once; epoch must differ from every earlier call's on the same flags; fail gets
+// -1 if an internal wait ran out.
 int potrf_flag_count(int m);
 size_t potrf_work_doubles(int m);
-void launch_potrf(int m, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail, hipStream_t st);
-void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *flags, int epoch, int *fail,
-                       hipStream_t st);
+void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
+void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
 // R^T x = u with R the factor left in B and u read with stride ustride
 void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *u, int64_t ustride, double *x, int *flags,
                       int epoch, int *fail, hipStream_t st);
