@@ -51,13 +51,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // first product so one memory latency covers the whole tile.
 struct TileIdx {
     int lane, li, lk, qr, qc;
-    __device__ TileIdx() {
+    __device__ TileIdx() : TileIdx(int(threadIdx.x) / 64) {}
+    __device__ explicit TileIdx(int quadrant) {   // quadrant w: rows 32 (w % 2), columns 32 (w / 2)
         lane = threadIdx.x % 64;
-        const int w = threadIdx.x / 64;
         li = lane % 16;
         lk = lane / 16;
-        qr = 32 * (w % 2);
-        qc = 32 * (w / 2);
+        qr = 32 * (quadrant % 2);
+        qc = 32 * (quadrant / 2);
     }
     __device__ int row(int ti) const { return qr + 16 * ti + li; }                 // tile row of acc[ti][.]
     __device__ int col(int tj, int r) const { return qc + 16 * tj + 4 * r + lk; }   // tile column of element r
@@ -236,21 +236,22 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
     // reports a failed pivot and stores R_ss.
     const int I = s + int(blockIdx.x), I0 = NB * I;
     const bool diag = (I == s);
-    // a tile of column block s with panel s-1 applied, in the accumulator layout
-    auto stage = [&](int R0, bool lower, double (&c)[2][2][4]) {
+    // quadrant tq of a tile of column block s with panel s-1 applied, in the
+    // accumulator layout
+    auto stage = [&](const TileIdx &tq, int R0, bool lower, double (&c)[2][2][4]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gi = R0 + t.row(a), gk = t.col(b, r);
+                    const int gi = R0 + tq.row(a), gk = tq.col(b, r);
                     c[a][b][r] = (gi < rows && gk < jb && (!lower || gi >= J0 + gk)) ? B[gi + ldb * (J0 + gk)] : 0.0;
                 }
         if (s >= 1) {
             d4 acc[2][2];
             zero_acc(acc);
-            tile_mma(t, B, ldb, R0, rows, J0 - NB, B, ldb, J0, m, J0 - NB, NB, acc);
+            tile_mma(tq, B, ldb, R0, rows, J0 - NB, B, ldb, J0, m, J0 - NB, NB, acc);
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -259,25 +260,25 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
                     for (int r = 0; r < 4; ++r) c[a][b][r] -= acc[a][b][r];
         }
     };
-    auto to_lds = [&](const double (&c)[2][2][4]) {
+    auto to_lds = [&](const TileIdx &tq, const double (&c)[2][2][4]) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) S[t.row(a) * LDS_LD + t.col(b, r)] = c[a][b][r];
+                for (int r = 0; r < 4; ++r) S[tq.row(a) * LDS_LD + tq.col(b, r)] = c[a][b][r];
     };
-    // the updated panel tile (I, s) is parked in its own place in B while the diagonal
-    // tile is factorised (registers are short there); each thread reads back exactly
-    // the entries it wrote
-    auto own_rw = [&](double (&c)[2][2][4], bool put) {
+    // the updated panel tile (I, s) is formed by waves 1..3 while wave 0 factorises the
+    // diagonal tile, and parked in its own place in B until S is free again; each
+    // thread reads back exactly the entries it wrote
+    auto own_rw = [&](const TileIdx &tq, double (&c)[2][2][4], bool put) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int gi = I0 + t.row(a), gk = t.col(b, r);
+                    const int gi = I0 + tq.row(a), gk = tq.col(b, r);
                     const bool in = gi < rows && gk < jb;
                     if (put) {
                         if (in) B[gi + ldb * (J0 + gk)] = c[a][b][r];
@@ -286,17 +287,24 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
                     }
                 }
     };
+    const int wv = tid >> 6;
+    // quadrants of the panel tile: waves 1..3 their own, wave 1 also quadrant 0
     {
         double cd[2][2][4];
-        stage(J0, true, cd);
-        if (!diag) {
-            double co[2][2][4];
-            stage(I0, false, co);
-            own_rw(co, true);
-        }
-        to_lds(cd);
+        stage(t, J0, true, cd);
+        to_lds(t, cd);
     }
     __syncthreads();
+    if (tid >= 64 && !diag) {
+        double co[2][2][4];
+        stage(t, I0, false, co);
+        own_rw(t, co, true);
+        if (wv == 1) {
+            const TileIdx t0(0);
+            stage(t0, I0, false, co);
+            own_rw(t0, co, true);
+        }
+    }
     if (tid < 64) {
         __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
         // rows of the tile below the block's own jb rows (right-hand-side rows riding
@@ -361,7 +369,7 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
     // on the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2); F replaces
     // the intermediate in Eb, the panel tile replaces R_ss in S
     {
-        const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+        const int l = tid & 63, li = l & 15, lk = l >> 4;
         const int bi = wv >> 1, bj = wv & 1;
         const bool rowok = 32 + 16 * bi + li < jb;
         d4 e = d4{0.0, 0.0, 0.0, 0.0};
@@ -375,8 +383,16 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
 #pragma unroll
         for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = e[r];
         __syncthreads();
-        double co[2][2][4];
-        own_rw(co, false);   // in flight during the second product
+        if (wv >= 1) {   // S is free again: the parked panel tile into S
+            double co[2][2][4];
+            own_rw(t, co, false);
+            to_lds(t, co);
+            if (wv == 1) {
+                const TileIdx t0(0);
+                own_rw(t0, co, false);
+                to_lds(t0, co);
+            }
+        }
         d4 f = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
@@ -388,7 +404,6 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = -f[r];
-        to_lds(co);
     }
     __syncthreads();
     // X = C R_ss^{-T}: R^{-1}(col, k) is A^{-1} (col, k < 32), zero (col < 32 <= k),
