@@ -336,23 +336,28 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
         } else {
             invd[lane] = 1.0 / dg;
             __builtin_amdgcn_s_waitcnt(0xc07f);
-            // inverses of the diagonal blocks A = R(0:32, 0:32) (lanes 0..31) and
-            // C = R(32:64, 32:64) (lanes 32..63): lane j forms column j by forward
-            // substitution, each row's sum split over four partial sums to shorten the
-            // dependent chain; rows beyond the block's jb rows are taken as identity rows
-            const int hb = lane >> 5, j = lane & 31, rb = 32 * hb;
-            double x[32];
+            // inverses of the four 16 x 16 diagonal blocks of R_ss: lane 16 g + j forms
+            // column j of block g by forward substitution (four partial sums per row);
+            // rows beyond the block's jb rows are taken as identity rows.  Blocks 0, 1
+            // are the diagonal of A^{-1} = R(0:32, 0:32)^{-1} (in Ai), blocks 2, 3 that
+            // of C^{-1} = R(32:64, 32:64)^{-1} (in Ci); above them A^{-1} and C^{-1} are zero.
+            const int g = lane >> 4, j = lane & 15, rb = 16 * g;
+            double x[16];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < 16; ++i) {
                 double p[4] = {(i == j) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int k = 0; k < i; ++k) p[k & 3] = fma(-S[(rb + i) * LDS_LD + rb + k], x[k], p[k & 3]);
                 const double sacc = (p[0] + p[1]) + (p[2] + p[3]);
                 x[i] = (rb + i < jb) ? sacc * invd[rb + i] : ((i == j) ? 1.0 : 0.0);
             }
-            double *Xo = hb ? Ci : Ai;
+            double *Xo = (g < 2) ? Ai : Ci;
+            const int o = 16 * (g & 1);
 #pragma unroll
-            for (int i = 0; i < 32; ++i) Xo[i * 33 + j] = x[i];
+            for (int i = 0; i < 16; ++i) {
+                Xo[(o + i) * 33 + o + j] = x[i];
+                if (o == 0) Xo[i * 33 + 16 + j] = 0.0;
+            }
         }
         __builtin_amdgcn_s_setprio(0);
     }
@@ -365,6 +370,34 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
         if (s >= 1) put_diag(B, ldb, rows, m, s - 1, Rscr);
         return;
     }
+    // the lower-left 16 x 16 blocks of A^{-1} and C^{-1}: -D1^{-1} (R10 D0^{-1}) by wave 0
+    // and -D3^{-1} (R32 D2^{-1}) by wave 1, through Eb
+    if (wv < 2) {
+        const int l = tid & 63, li = l & 15, lk = l >> 4;
+        double *Xb = wv ? Ci : Ai;
+        const int r0 = wv ? 32 : 0;   // row / column offset of the 32 x 32 block in R_ss
+        d4 e = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lk;
+            e = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(r0 + 16 + li) * LDS_LD + r0 + k], Xb[k * 33 + li], e, 0, 0,
+                                                     0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Eb[(16 * wv + 4 * r + lk) * 33 + li] = e[r];
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        d4 f = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lk;
+            f = __builtin_amdgcn_mfma_f64_16x16x4f64(Xb[(16 + li) * 33 + 16 + k], Eb[(16 * wv + k) * 33 + li], f, 0,
+                                                     0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xb[(16 + 4 * r + lk) * 33 + li] = -f[r];
+    }
+    __syncthreads();
     // R^{-1}(32:64, 0:32) = F = -C^{-1} (R(32:64, 0:32) A^{-1}): two 32 x 32 x 32 products
     // on the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2); F replaces
     // the intermediate in Eb, the panel tile replaces R_ss in S
