@@ -171,79 +171,62 @@ k_sum_partials(int n, int nparts, const double *__restrict__ part, const int *__
     }
 }
 
-// dX on E, block-tiled: for storage block b and a chunk of d, partial sums of
-// T(R_b, cols_b) = Z(R_b, :) Y^{-1}(:, cols_b) and T(cols_b, R_b) with T = X^ dY Y^{-1}
-// (Z = X^ dY column-major).  part holds [chunk][2][nslot].
-constexpr int kDxTile = 32;
-constexpr int kDxRows = 64;
+// dX on E, block-tiled: for storage block b and a chunk of 256 values of d, partial
+// sums of T(R_b, cols_b) = Z(R_b, :) Y^{-1}(:, cols_b) and T(cols_b, R_b)^T =
+// Y^{-1}(R_b, :) Z(cols_b, :)^T with T = X^ dY Y^{-1} (Z = X^ dY column-major; Y^{-1} is
+// symmetric, so both products read rows of column-major matrices: coalesced).  part
+// holds [chunk][2][nslot].  On the FP64 MFMA (16 x 16 x 4; lane l supplies A(l % 16,
+// l / 16) and B(l / 16, l % 16), element r of the result is C(4 r + l / 16, l % 16)):
+// wave w owns the 16-row tiles w, w + 4, ... of the panel and both 16-column tiles.
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kDxChunk = 256;
+
 __global__ void __launch_bounds__(256)
-k_dX_block(int n, int nslot_i, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
-           const int *__restrict__ bl_rows, const int64_t *__restrict__ bl_off, const double *__restrict__ Z,
-           const double *__restrict__ Yi, int dchunk, double *__restrict__ part) {
-    __shared__ double Zr[kDxRows * (kDxTile + 1)];   // rows x tile
-    __shared__ double Yr[kDxTile * (kDxRows + 1)];   // tile x rows
-    __shared__ double Zc[32 * (kDxTile + 1)];        // w x tile
-    __shared__ double Yc[kDxTile * 33];              // tile x w
+k_dX_mma(int n, int nslot_i, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+         const int *__restrict__ bl_rows, const int64_t *__restrict__ bl_off, const double *__restrict__ Z,
+         const double *__restrict__ Yi, double *__restrict__ part) {
     const int b = blockIdx.x, ch = blockIdx.y;
     const int F = bl_first[b], w = bl_first[b + 1] - F;
     const int64_t r0 = bl_rptr[b];
     const int h = int(bl_rptr[b + 1] - r0);
-    const int *R = bl_rows + r0;
-    const int tid = threadIdx.x;
-    const int64_t off = bl_off[b];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int c0 = min(F + li, n - 1), c1 = min(F + 16 + li, n - 1);   // clamped: loads stay in range
+    const bool pc0 = li < w, pc1 = 16 + li < w;
+    const int d_begin = ch * kDxChunk;
     double *p1 = part + int64_t(ch) * 2 * nslot_i;
     double *p2 = p1 + nslot_i;
-    const int d_begin = ch * dchunk, d_end = min(n, d_begin + dchunk);
-    for (int pt = 0; pt < h; pt += kDxRows) {          // row tiles
-        const int hh = min(kDxRows, h - pt);
-        const int nout = hh * w;                       // <= 64 x 32: 8 outputs per thread
-        double a1[8], a2[8];
+    const int64_t off = bl_off[b];
+    for (int rt = wv; 16 * rt < h; rt += 4) {   // 16-row tiles of the panel
+        const int p = 16 * rt + li;             // panel row supplied by this lane
+        const int row = bl_rows[r0 + min(p, h - 1)];
+        const bool prow = p < h;
+        d4 o1[2], o2[2];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a1[t] = a2[t] = 0.0;
-        for (int d0 = d_begin; d0 < d_end; d0 += kDxTile) {
-            const int nd = min(kDxTile, d_end - d0);
-            for (int idx = tid; idx < kDxRows * kDxTile; idx += blockDim.x) {
-                const int p = idx % kDxRows, dd = idx / kDxRows;
-                Zr[p * (kDxTile + 1) + dd] = (dd < nd && p < hh) ? Z[R[pt + p] + int64_t(n) * (d0 + dd)] : 0.0;
-            }
-            for (int idx = tid; idx < kDxRows * kDxTile; idx += blockDim.x) {
-                const int dd = idx % kDxTile, p = idx / kDxTile;
-                Yr[dd * (kDxRows + 1) + p] = (dd < nd && p < hh) ? Yi[(d0 + dd) + int64_t(n) * R[pt + p]] : 0.0;
-            }
-            for (int idx = tid; idx < 32 * kDxTile; idx += blockDim.x) {
-                const int c = idx % 32, dd = idx / 32;
-                Zc[c * (kDxTile + 1) + dd] = (dd < nd && c < w) ? Z[(F + c) + int64_t(n) * (d0 + dd)] : 0.0;
-            }
-            for (int idx = tid; idx < 32 * kDxTile; idx += blockDim.x) {
-                const int dd = idx % kDxTile, c = idx / kDxTile;
-                Yc[dd * 33 + c] = (dd < nd && c < w) ? Yi[(d0 + dd) + int64_t(n) * (F + c)] : 0.0;
-            }
-            __syncthreads();
+        for (int t = 0; t < 2; ++t) o1[t] = o2[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int ks = 0; ks < kDxChunk / 4; ++ks) {
+            const int dd = d_begin + 4 * ks + lk;
+            const bool pd = dd < n;
+            const int64_t cd = int64_t(n) * min(dd, n - 1);
+            const double za = Z[row + cd], ya = Yi[row + cd];
+            const double y0 = Yi[c0 + cd], y1 = Yi[c1 + cd], z0 = Z[c0 + cd], z1 = Z[c1 + cd];
+            const double a1 = (prow && pd) ? za : 0.0, a2 = (prow && pd) ? ya : 0.0;
+            o1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, (pc0 && pd) ? y0 : 0.0, o1[0], 0, 0, 0);
+            o1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, (pc1 && pd) ? y1 : 0.0, o1[1], 0, 0, 0);
+            o2[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, (pc0 && pd) ? z0 : 0.0, o2[0], 0, 0, 0);
+            o2[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, (pc1 && pd) ? z1 : 0.0, o2[1], 0, 0, 0);
+        }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int o = tid + 256 * t;
-                const int p = o % kDxRows, c = o / kDxRows;   // c < 32 always
-                double s1 = 0.0, s2 = 0.0;
-#pragma unroll 8
-                for (int dd = 0; dd < kDxTile; ++dd) {
-                    s1 += Zr[p * (kDxTile + 1) + dd] * Yc[dd * 33 + c];
-                    s2 += Zc[c * (kDxTile + 1) + dd] * Yr[dd * (kDxRows + 1) + p];
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pr = 16 * rt + 4 * r + lk, c = 16 * t + li;
+                if (pr < h && c < w) {
+                    const int64_t sl = off + pr + int64_t(h) * c;
+                    p1[sl] = o1[t][r];
+                    p2[sl] = o2[t][r];
                 }
-                a1[t] += s1;
-                a2[t] += s2;
             }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int o = tid + 256 * t;
-            const int p = o % kDxRows, c = o / kDxRows;
-            if (p < hh && c < w) {
-                const int64_t sl = off + (pt + p) + int64_t(h) * c;
-                p1[sl] = a1[t];
-                p2[sl] = a2[t];
-            }
-        }
     }
 }
 
@@ -335,13 +318,13 @@ void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *X
                        (const double *)part, d.had_pos, hcol);
 }
 
-int dX_chunks(const DevStruct &d) { return (d.n + 255) / 256; }
+int dX_chunks(const DevStruct &d) { return (d.n + kDxChunk - 1) / kDxChunk; }
 
 void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, const double *Xbar, double beta_mu,
                        double *part, double *dX, hipStream_t st) {
     const int nch = dX_chunks(d);
-    hipLaunchKernelGGL(k_dX_block, dim3(d.nb, nch), dim3(256), 0, st, d.n, int(d.nslot), d.bl_first, d.bl_rptr,
-                       d.bl_rows, d.bl_off, Z, Yi, 256, part);
+    hipLaunchKernelGGL(k_dX_mma, dim3(d.nb, nch), dim3(256), 0, st, d.n, int(d.nslot), d.bl_first, d.bl_rptr,
+                       d.bl_rows, d.bl_off, Z, Yi, part);
     hipLaunchKernelGGL(k_dX_finish, dim3(grid_cap(d.nslot, 256)), dim3(256), 0, st, d.nslot, d.n, nch, d.slot_row,
                        d.slot_col, (const double *)part, Yi, Xbar, beta_mu, dX);
 }
