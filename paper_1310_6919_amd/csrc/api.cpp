@@ -530,6 +530,38 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             ag_cptr[j + 1] = int64_t(ag_row.size());
         }
     }
+    // the same pattern by groups of 32 columns (row union and a slot per union row and
+    // column); small unions go to the MFMA path of X^ M
+    const int nzg = (n + 31) / 32;
+    std::vector<int64_t> zg_ptr(nzg + 1, 0);
+    std::vector<int> zg_rows, zg_slot, zg_mma, zg_col;
+    for (int g = 0; g < nzg; ++g) {
+        const int c0 = 32 * g, c1 = std::min(n, c0 + 32);
+        std::vector<int> u;
+        for (int c = c0; c < c1; ++c)
+            for (int64_t t = ag_cptr[c]; t < ag_cptr[c + 1]; ++t) u.push_back(ag_row[t]);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        const int K = (int(u.size()) + 3) / 4 * 4;
+        if (K > kZmRows) {
+            zg_col.push_back(g);
+            zg_ptr[g + 1] = zg_ptr[g];
+            continue;
+        }
+        zg_mma.push_back(g);
+        const size_t base = zg_slot.size();
+        zg_slot.resize(base + size_t(K) * 32, -1);
+        for (int k = 0; k < K; ++k) zg_rows.push_back(k < int(u.size()) ? u[k] : (u.empty() ? 0 : u.back()));
+        for (int c = c0; c < c1; ++c)
+            for (int64_t t = ag_cptr[c]; t < ag_cptr[c + 1]; ++t) {
+                const int k = int(std::lower_bound(u.begin(), u.end(), ag_row[t]) - u.begin());
+                zg_slot[base + size_t(k) * 32 + (c - c0)] = ag_slot[t];
+            }
+        zg_ptr[g + 1] = zg_ptr[g] + K;
+    }
+    d.nzg = nzg;
+    d.nzg_mma = int(zg_mma.size());
+    d.nzg_col = int(zg_col.size());
     // ---- uploads
     TRY(upload(h, &d.bl_first, S.bl_first));
     TRY(upload(h, &d.bl_rptr, S.bl_rptr));
@@ -580,6 +612,11 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.ag_cptr, ag_cptr));
     TRY(upload(h, &d.ag_row, ag_row));
     TRY(upload(h, &d.ag_slot, ag_slot));
+    TRY(upload(h, &d.zg_ptr, zg_ptr));
+    TRY(upload(h, &d.zg_rows, zg_rows));
+    TRY(upload(h, &d.zg_slot, zg_slot));
+    TRY(upload(h, &d.zg_mma, zg_mma));
+    TRY(upload(h, &d.zg_col, zg_col));
     // ---- workspace
     const size_t ns = size_t(S.nslot), nn = size_t(n) * n;
     h->ldb = int64_t(m) + 1;   // row m carries the SCE right-hand side through the factorisation

@@ -100,7 +100,19 @@ struct DevStruct {
     const int64_t *ag_cptr = nullptr;   // n + 1
     const int *ag_row = nullptr;
     const int *ag_slot = nullptr;
+    // the same pattern by groups of 32 consecutive columns: the union of the rows of a
+    // group (padded to a multiple of 4) and, per union row and column of the group, the
+    // slot of the entry (-1: none).  Groups whose union has at most kZmRows rows are
+    // formed as small dense products on the MFMA; the others column by column.
+    int nzg = 0;                        // ceil(n / 32)
+    const int64_t *zg_ptr = nullptr;    // nzg + 1: offsets into zg_rows (zg_slot: 32 per row)
+    const int *zg_rows = nullptr;
+    const int *zg_slot = nullptr;
+    int nzg_mma = 0, nzg_col = 0;
+    const int *zg_mma = nullptr;        // groups on the MFMA path
+    const int *zg_col = nullptr;        // groups on the column path
 };
+constexpr int kZmRows = 128;
 
 // ---- assembly and vectors (k_vec.hip)
 // out[s] = sum_t asm_val[t] * coef_k  + c1 * in1[s]; coef_0 = a0, coef_k = -y[k-1]
