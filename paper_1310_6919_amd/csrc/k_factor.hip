@@ -447,6 +447,64 @@ k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_ma
     if (tid == 0) alpha_cl[r] = res;
 }
 
+// The same step lengths for cliques of at most 32 members, one wave per clique (four
+// per workgroup) and no barriers: lane i holds row i of the clique block (in the
+// reversed order Algorithm 1 factorises in) and of the direction; each test is a
+// readlane elimination as in k_sn_chol_wave, a pivot that is not positive and
+// finite leaving a NaN on the diagonal.  The bisection is the same.
+__global__ void __launch_bounds__(256)
+k_alpha_cl_wave(int ncl, const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
+                const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
+                double *__restrict__ alpha_cl) {
+    const int r = 4 * int(blockIdx.x) + int(threadIdx.x >> 6);
+    if (r >= ncl) return;   // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
+    const int *map = cl_map + cl_map_ptr[r];
+    auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
+    double x[32], dx[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const bool in = lane < c && k <= lane;
+        const int sl = in ? map[pk(c - 1 - k, c - 1 - lane)] : 0;
+        x[k] = in ? Xbar[sl] : (lane == k ? 1.0 : 0.0);
+        dx[k] = in ? dX[sl] : 0.0;
+    }
+    auto test = [&](double al) -> bool {
+        double a[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) a[k] = fma(al, dx[k], x[k]);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k < c) {   // uniform
+                const double d = lane_bcast(a[k], k);
+                const double inv = rsqrt_newton(d);
+                const double l = (lane >= k) ? a[k] * inv : 0.0;
+                a[k] = l;
+                elim_step_bcast(a, l, k, 0);
+            }
+        }
+        double dg = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k == lane) dg = a[k];
+        return __ballot(lane < c && !((dg > 0.0) && isfinite(dg))) == 0ull;
+    };
+    double res;
+    if (test(1.0)) {
+        res = 1.0;
+    } else {
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 52; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (test(mid)) lo = mid; else hi = mid;
+        }
+        res = lo;
+    }
+    if (lane == 0) alpha_cl[r] = res;
+}
+
 // After a round of candidate tests (fail[c] == 0: Y + a_c dY positive definite),
 // keep the longest prefix of successful test points and narrow
 // bracket = (lo, hi, settled, twin): twin is the candidate index holding the
@@ -569,8 +627,12 @@ void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int
 
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX, double *alpha_cl,
                           double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
-                       alpha_cl);
+    if (d.max_clique <= 32)
+        hipLaunchKernelGGL(k_alpha_cl_wave, dim3((d.ncl + 3) / 4), dim3(256), 0, st, d.ncl, d.cl_ptr, d.cl_map_ptr,
+                           d.cl_map, Xbar, dX, alpha_cl);
+    else
+        hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
+                           alpha_cl);
     hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, alpha_cl, out);
 }
 
