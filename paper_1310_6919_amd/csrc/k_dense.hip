@@ -501,6 +501,25 @@ k_trsv_bwd_chain(const double *__restrict__ R, int64_t ldb, int m, const double 
         const int i = idx % NB, j = idx / NB;   // consecutive threads: consecutive rows of column j
         D[i * LDS_LD + j] = (i < jb && j <= i) ? R[(J0 + i) + ldb * (J0 + j)] : 0.0;
     }
+    __syncthreads();
+    // wave 0, while the later blocks of x are still being formed: lane j holds column j
+    // of R_JJ^{-1} (forward substitution, four partial sums per row; identity rows
+    // beyond jb), so that x_J = R_JJ^{-T} v becomes one product once v is known
+    double rinv[NB];
+    if (tid < NB) {
+        xk[tid] = (tid < jb) ? 1.0 / D[tid * LDS_LD + tid] : 1.0;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double p4[4] = {(i == tid) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < i; ++k) p4[k & 3] = fma(-D[i * LDS_LD + k], rinv[k], p4[k & 3]);
+            const double sacc = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+            rinv[i] = (i < jb) ? sacc * xk[i] : ((i == tid) ? 1.0 : 0.0);
+        }
+    }
+    __syncthreads();
     const int jj = tid % NB, pg = tid / NB;   // column jj of the block, rows pg*16 .. pg*16+15 of tile K
     double acc = 0.0;
     for (int K = T - 1; K > J; --K) {
@@ -532,15 +551,14 @@ k_trsv_bwd_chain(const double *__restrict__ R, int64_t ldb, int m, const double 
         const int lane = tid;
         double v = (lane < jb) ? u[(J0 + lane) * ustride] : 0.0;
         v -= part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-        // R_JJ^T x_J = v, from the last row up: x_i = v_i / R(i, i), then
-        // v_j -= R(i, j) x_i for j < i
-        const double dii = (lane < jb) ? D[lane * LDS_LD + lane] : 1.0;
+        // x_J(i) = sum_k R_JJ^{-1}(k, i) v_k, v broadcast through LDS
+        xk[lane] = v;
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 63; i >= 0; --i) {
-            const double xi = lane_bcast(v / dii, i);
-            if (lane == i) v = xi;
-            else if (lane < i) v = fma(-D[i * LDS_LD + lane], xi, v);
-        }
+        for (int k = 0; k < NB; ++k) p4[k & 3] = fma(rinv[k], xk[k], p4[k & 3]);
+        v = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         if (lane < jb) x[J0 + lane] = v;
         __threadfence();
         if (lane == 0) flag_release(&flags[J], epoch);
