@@ -68,6 +68,7 @@ struct sdpc_handle {
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
     double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
+    double *mwork = nullptr;  // partial results of the metrics
     double *ydw = nullptr, *ydw_dual = nullptr;   // row-major (Y, dY) tiles of the Y factor / dual step
     int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
                             // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
@@ -641,6 +642,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->pflags_b, size_t(potrf_flag_count(m))));
     TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->scal, 16));
+    TRY(dalloc(h, &h->mwork, metrics_work_doubles()));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
@@ -843,7 +845,7 @@ struct IterInfo {
 
 sdpc_status read_metrics(sdpc_handle *h, IterInfo &it) {
     DevStruct &d = h->d;
-    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, nullptr, h->st);
+    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, h->mwork, h->st);
     HIPCHK(h, hipGetLastError());
     double sc[8];
     HIPCHK(h, hipMemcpyAsync(sc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, h->st));

@@ -509,15 +509,17 @@ k_alpha_cl_wave(int ncl, const int64_t *__restrict__ cl_ptr, const int64_t *__re
 // keep the longest prefix of successful test points and narrow
 // bracket = (lo, hi, settled, twin): twin is the candidate index holding the
 // factor of Y + gamma lo dY, or -1 if that factor was not formed.
-__global__ void k_bracket(int ntest, int round, double gamma, const int *__restrict__ fail,
-                          double *__restrict__ bracket) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (round > 0 && bracket[2] != 0.0) return;
-    int best = -1;
-    for (int c = 0; c < ntest; ++c) {
-        if (fail[c] != 0) break;
-        best = c;
-    }
+__global__ void __launch_bounds__(1024) k_bracket(int ntest, int round, double gamma, const int *__restrict__ fail,
+                                                   double *__restrict__ bracket) {
+    __shared__ int first;   // first test point that failed (ntest if none)
+    if (round > 0 && bracket[2] != 0.0) return;   // uniform: settled
+    if (threadIdx.x == 0) first = ntest;
+    __syncthreads();
+    for (int c = threadIdx.x; c < ntest; c += blockDim.x)
+        if (fail[c] != 0) atomicMin(&first, c);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int best = first - 1;   // the longest prefix of test points that passed
     auto cand = [&](int c) { return cand_alpha(c, ntest, round, gamma, bracket); };
     if (round == 0) {
         if (best == ntest - 1) {   // alpha = 1 passes; its twin (candidate ntest) is gamma * 1
@@ -611,7 +613,7 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
                                d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket,
                                r, ntest[r], gamma, cand, d.nslot, fail);
         }
-        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(64), 0, st, ntest[r], r, gamma, (const int *)fail, bracket);
+        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(1024), 0, st, ntest[r], r, gamma, (const int *)fail, bracket);
     }
 }
 

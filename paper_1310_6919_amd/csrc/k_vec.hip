@@ -57,21 +57,26 @@ __device__ double block_max(double v, double *sh) {
 }
 
 // scal[0] = A_0 . X, scal[1] = b . z, scal[2] = max_k |b_k - A_k . X|,
-// scal[3] = max |G|, scal[4] = X . Y (on E), scal[5] = 1 if anything non-finite
+// scal[3] = max |G|, scal[4] = X . Y (on E), scal[5] = 1 if anything non-finite.
+// kMetricsGroups workgroups write partial results part[8 g + i]; k_metrics_final
+// combines them in a fixed order.
+constexpr int kMetricsGroups = 64;
+
 __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const int64_t *__restrict__ con_ptr,
                                                   const int *__restrict__ con_slot,
                                                   const double *__restrict__ con_val,
                                                   const double *__restrict__ b, const double *__restrict__ wE,
                                                   const double *__restrict__ X, const double *__restrict__ Y,
                                                   const double *__restrict__ z, const double *__restrict__ G,
-                                                  double *__restrict__ scal) {
+                                                  double *__restrict__ part) {
     __shared__ double sh[1024];
     const int t = threadIdx.x;
+    const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + t, step = int64_t(gridDim.x) * blockDim.x;
     double pobj = 0.0, bz = 0.0, rmax = 0.0, gmax = 0.0, xy = 0.0;
     bool bad = false;
     // A_0 . X over all threads (A_0 carries the whole aggregate pattern)
-    for (int64_t e = con_ptr[0] + t; e < con_ptr[1]; e += blockDim.x) pobj += con_val[e] * X[con_slot[e]];
-    for (int k = 1 + t; k <= m; k += blockDim.x) {
+    for (int64_t e = con_ptr[0] + i0; e < con_ptr[1]; e += step) pobj += con_val[e] * X[con_slot[e]];
+    for (int64_t k = 1 + i0; k <= m; k += step) {
         double a = 0.0;
         for (int64_t e = con_ptr[k]; e < con_ptr[k + 1]; ++e) a += con_val[e] * X[con_slot[e]];
         const double r = b[k - 1] - a;
@@ -79,7 +84,7 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
         bz += b[k - 1] * z[k - 1];
         bad |= !isfinite(z[k - 1]);
     }
-    for (int64_t s = t; s < nslot; s += blockDim.x) {
+    for (int64_t s = i0; s < nslot; s += step) {
         const double w = wE[s];
         xy += w * X[s] * Y[s];
         gmax = fmax(gmax, fabs(G[s]));
@@ -92,13 +97,29 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
     xy = block_sum(xy, sh);
     const double nb = block_max(bad ? 1.0 : 0.0, sh);
     if (t == 0) {
-        scal[0] = pobj;
-        scal[1] = bz;
-        scal[2] = rmax;
-        scal[3] = gmax;
-        scal[4] = xy;
-        scal[5] = nb;
+        double *pp = part + 8 * blockIdx.x;
+        pp[0] = pobj;
+        pp[1] = bz;
+        pp[2] = rmax;
+        pp[3] = gmax;
+        pp[4] = xy;
+        pp[5] = nb;
     }
+}
+
+__global__ void k_metrics_final(int ng, const double *__restrict__ part, double *__restrict__ scal) {
+    if (threadIdx.x != 0) return;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < ng; ++g) {
+        const double *pp = part + 8 * g;
+        v[0] += pp[0];
+        v[1] += pp[1];
+        v[2] = fmax(v[2], pp[2]);
+        v[3] = fmax(v[3], pp[3]);
+        v[4] += pp[4];
+        v[5] = fmax(v[5], pp[5]);
+    }
+    for (int i = 0; i < 6; ++i) scal[i] = v[i];
 }
 
 // x += coef dx, with coef = scale * alpha[0] when alpha is given (a step length
@@ -145,12 +166,15 @@ void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, 
                        d.asm_k, d.asm_val, y, a0, c1, in1, out);
 }
 
+size_t metrics_work_doubles() { return size_t(8) * kMetricsGroups; }
+
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z, double *G,
-                    double *scal, double * /*work*/, hipStream_t st) {
+                    double *scal, double *work, hipStream_t st) {
     // G = A_0 - sum z_k A_k - Y
     launch_assemble(d, z, 1.0, -1.0, Y, G, st);
-    hipLaunchKernelGGL(k_metrics, dim3(1), dim3(1024), 0, st, d.m, d.nslot, d.con_ptr, d.con_slot,
-                       d.con_val, d.b, d.wE, X, Y, z, G, scal);
+    hipLaunchKernelGGL(k_metrics, dim3(kMetricsGroups), dim3(1024), 0, st, d.m, d.nslot, d.con_ptr, d.con_slot,
+                       d.con_val, d.b, d.wE, X, Y, z, G, work);
+    hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(64), 0, st, kMetricsGroups, (const double *)work, scal);
 }
 
 void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha, double scale,
