@@ -33,12 +33,13 @@ using namespace sdpc;
 
 namespace {
 
-// Dual step: round 0 tests 1024 log-spaced points (neighbours 1.8% apart) and the
-// gamma twin of alpha = 1; round 1 tests 256 even points inside the bracket
-// (relative spacing ~7e-5) and their 256 gamma twins.  One wave per candidate.
+// Dual step: round 0 tests 1023 log-spaced points (neighbours 1.8% apart) and the
+// gamma twin of alpha = 1, 1024 candidates: one wave per SIMD of the chip; round 1
+// tests 256 even points inside the bracket (relative spacing ~7e-5) and their 256
+// gamma twins.  One wave per candidate.
 constexpr int kDualRounds = 2;
-constexpr int kDualTest[kDualRounds] = {1024, 256};
-constexpr int kCand = 1025;      // the most candidates of a round
+constexpr int kDualTest[kDualRounds] = {1023, 256};
+constexpr int kCand = 1024;      // the most candidates of a round
 
 struct Timer {
     hipEvent_t a{}, b{};
