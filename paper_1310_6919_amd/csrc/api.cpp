@@ -84,7 +84,7 @@ struct sdpc_handle {
     double *pwork = nullptr;   // diagonal factors of the SCM Cholesky waiting for the next launch
     int epoch = 0;                                    // last epoch used on those flags
     int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
-    bool xside_ready = false;   // Lhat, its diagonal inverses and X^ already belong to the current X
+    bool xside_ready = false;   // Lhat and its diagonal inverses already belong to the current X
     int iters = 0;
 };
 
@@ -802,10 +802,9 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
         launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
     }
     HIPCHK(h, hipEventRecord(h->evs[2], st));
-    if (xready)
-        launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, nullptr, nullptr, nullptr, st);
-    else
-        launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
+    // Y^{-1} and X^ in one launch: the two walks are latency-bound and fill each
+    // other's idle compute units
+    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
     h->xside_ready = false;
     HIPCHK(h, hipEventRecord(h->evs[3], st));
     if (d.hadamard)
@@ -914,13 +913,12 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     launch_zcol(d, h->Xh, h->dY, h->W, st);
     launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
     launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
-    // Step 4 for X with alpha_p still on the device, then the X side of the next
-    // iteration (Algorithm 1, Lhat's diagonal inverses, X^) while the dual step runs
+    // Step 4 for X with alpha_p still on the device, then Algorithm 1 and Lhat's
+    // diagonal inverses for the next iteration while the dual step runs
     const double gm = h->prm.gamma;
     launch_axpy_E(d, h->X, h->dX, h->scal + 8, gm, st);
     launch_algorithm1(d, h->X, h->Lhat, h->flags + kCand + 3, st);
     launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand + 4, st);
-    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st);
     HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
     HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
     // Step 4 for Y and z (alpha_d = bracket[0] on the device; the same fma as the
