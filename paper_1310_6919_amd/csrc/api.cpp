@@ -85,6 +85,8 @@ struct sdpc_handle {
     int epoch = 0;                                    // last epoch used on those flags
     int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
     bool xside_ready = false;   // Lhat and its diagonal inverses already belong to the current X
+    bool metrics_ready = false; // msc holds the metrics of the current iterate (read with the last step)
+    double msc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int iters = 0;
 };
 
@@ -753,9 +755,12 @@ int read_flag(sdpc_handle *h, int idx) {
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
 // Flags of the phases, checked after the launch sequence has completed.
-sdpc_status check_flags(sdpc_handle *h, bool potrf) {
+sdpc_status check_flags(sdpc_handle *h, bool potrf, const int *fl_read = nullptr) {
     int fl[kCand + 8];
-    HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl_read)
+        std::memcpy(fl, fl_read, sizeof(fl));
+    else
+        HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
     if (fl[kCand + 5])
         return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[kCand + 5] - 1) + ")");
     if (fl[kCand + 1])
@@ -845,11 +850,16 @@ struct IterInfo {
 
 sdpc_status read_metrics(sdpc_handle *h, IterInfo &it) {
     DevStruct &d = h->d;
-    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, h->mwork, h->st);
-    HIPCHK(h, hipGetLastError());
     double sc[8];
-    HIPCHK(h, hipMemcpyAsync(sc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (h->metrics_ready) {   // formed and read back with the previous step
+        std::memcpy(sc, h->msc, sizeof(sc));
+        h->metrics_ready = false;
+    } else {
+        launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, h->mwork, h->st);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipMemcpyAsync(sc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    }
     if (sc[5] != 0.0) return fail(h, SDPC_E_NUMERIC, "non-finite iterate");
     it.pobj = sc[0];
     it.dobj = sc[1];
@@ -925,13 +935,20 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     // dual step's twin candidates, whose factor of the new Y is then reused)
     launch_axpy_E(d, h->Y, h->dY, h->alphas, gm, st);
     launch_axpy_vec(d.m, h->z, h->dz, h->alphas, gm, st);
+    // the metrics of the new iterate (Step 1 of the next iteration), read back with
+    // the step lengths and the flags: one synchronisation per iteration
+    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, h->mwork, st);
     HIPCHK(h, hipGetLastError());
     double ap = 0.0, br[4] = {0, 0, 0, -1};
+    int fl[kCand + 8];
     HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipMemcpyAsync(br, h->alphas, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(h->msc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemcpyAsync(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
     read_scm_timing(h);
-    TRY(check_flags(h, true));
+    TRY(check_flags(h, true, fl));
+    h->metrics_ready = true;
     h->xside_ready = true;
     h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
     const double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
@@ -974,6 +991,7 @@ sdpc_status sdpc_reset(sdpc_handle *h) {
     h->iters = 0;
     h->next_cand = -1;
     h->xside_ready = false;
+    h->metrics_ready = false;
     return SDPC_OK;
 }
 
@@ -1090,6 +1108,7 @@ sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double 
     HIPCHK(h, hipGetLastError());
     h->next_cand = -1;
     h->xside_ready = false;
+    h->metrics_ready = false;
     return SDPC_OK;
 }
 
