@@ -88,6 +88,10 @@ typedef struct {
     int32_t ordering;          /* 0 natural, 1 minimum degree, 2 user_perm         (0)     */
     int32_t block_width;       /* widest storage block (columns), 1..32            (32)    */
     int32_t verbose;           /* 1: one line per iteration on stderr              (0)     */
+    int32_t pool_lds_bytes;    /* LDS budget per wave of the Y factorisation's pending-update
+                                  pool; larger pools live in device memory; 0 keeps them
+                                  there always                                    (32768)  */
+    int32_t reserved_;         /* 0                                                        */
     const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
                                   i-th (host, read at create)                              */
 } sdpc_params;

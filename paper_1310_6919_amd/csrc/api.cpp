@@ -155,6 +155,8 @@ sdpc_params sdpc_default_params(void) {
     p.ordering = 0;
     p.block_width = 32;
     p.verbose = 0;
+    p.pool_lds_bytes = 32 * 1024;
+    p.reserved_ = 0;
     p.user_perm = nullptr;
     return p;
 }
@@ -194,6 +196,8 @@ void sdpc_destroy(sdpc_handle *h) {
 static sdpc_status check_problem(const sdpc_problem *prob, sdpc_handle *h) {
     const int n = prob->n, m = prob->m;
     if (h->prm.block_width < 1 || h->prm.block_width > 32) return fail(h, SDPC_E_ARG, "block_width must be 1..32");
+    if (h->prm.pool_lds_bytes < 0 || h->prm.pool_lds_bytes > 64 * 1024)
+        return fail(h, SDPC_E_ARG, "pool_lds_bytes must be 0..65536");
     if (h->prm.gamma <= 0 || h->prm.gamma >= 1) return fail(h, SDPC_E_ARG, "gamma must be in (0,1)");
     const int64_t nnz = prob->ptr[m + 1];
     if (prob->ptr[0] != 0 || nnz < 0) return fail(h, SDPC_E_ARG, "ptr must start at 0");
@@ -330,8 +334,10 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
                 slot_u[s] = k;
             }
         }
-        // the pool fits when the factorisation's LDS stays within 32 KB (four waves per CU)
-        d.u_pool = (wave_chol_lds_bytes(S.max_h, used) <= 32 * 1024) ? 1 : 0;
+        // the pool is used when the factorisation's LDS stays within the budget (32 KiB by
+        // default: four waves per compute unit)
+        d.u_pool = (h->prm.pool_lds_bytes > 0 &&
+                    wave_chol_lds_bytes(S.max_h, used) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
         if (!d.u_pool) {   // one slot per target entry, in global memory
             int k = 0;
             for (int64_t s = 0; s < S.nslot; ++s)

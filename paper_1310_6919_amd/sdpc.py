@@ -35,7 +35,8 @@ class sdpc_params(C.Structure):
     _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("beta_feas", C.c_double),
                 ("beta_infeas", C.c_double), ("gamma", C.c_double), ("lambda0", C.c_double),
                 ("max_iter", C.c_int32), ("ordering", C.c_int32), ("block_width", C.c_int32),
-                ("verbose", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+                ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("reserved_", C.c_int32),
+                ("user_perm", C.POINTER(C.c_int32))]
 
 
 class sdpc_analysis(C.Structure):

@@ -257,6 +257,25 @@ def test_solve_matches_mc_oracle(name, tol):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["band_ragged", "normmin"])
+def test_update_slots_in_memory_match_pool(name):
+    """The one-wave factorisation keeps pending updates in an LDS pool or, beyond the
+    pool's LDS budget, in device memory: the same arithmetic in the same order, so
+    the whole solve is bit for bit the same either way."""
+    prob = CASES[name]()
+    out = []
+    for pool in (32 * 1024, 0):
+        h = _create(prob, pool_lds_bytes=pool)
+        r = h.sdpc_solve()
+        assert r["status"] == 0, r
+        X, Y, z = h.sdpc_get_solution()
+        out.append((r["iters"], host(X), host(Y), host(z)))
+        h.close()
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert np.array_equal(a, b)
+
+
 def test_solve_cycles_closed_form():
     for n in (5, 8, 13):
         e = sdpgen.cycle_graph(n)
