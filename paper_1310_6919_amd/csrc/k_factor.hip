@@ -204,6 +204,8 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
     double *Pr = sm;   // rows >= w of the factored panel, kPrLd doubles per row (prcap doubles)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
+    // each candidate is one long dependent chain: ahead of the waves of concurrent kernels
+    __builtin_amdgcn_s_setprio(3);
     if (dual && round > 0 && bracket[2] != 0.0) {   // settled: nothing to test
         if (lane == 0) fail[cand] = 0;
         return;
