@@ -145,6 +145,7 @@ def main():
     scm_per_iter = statistics.median([(r["t_scm_ms"] + r["t_chol_ms"]) / r["iters"] / 1e3 for r in results])
     potrf_ms = sum(r["t_potrf_ms"] for r in results) / max(1, sum(r["n_potrf"] for r in results))
     m = prob.m
+    launches = (m + 63) // 64
     flops = m ** 3 / 3.0
     achieved = flops / (potrf_ms * 1e-3) / 1e12
     traffic = None
@@ -181,16 +182,20 @@ def main():
             "pmatrix_and_steps": statistics.median([r["t_pmatrix_ms"] / r["iters"] for r in results]),
         },
         "roofline": {
-            "kernel": "SCM Cholesky: k_chol_step, one launch per 64-column block (%d per factorisation)"
-                      % ((m + 63) // 64),
+            "kernel": "SCM Cholesky: k_chol_step, one launch per 64-column block (%d per factorisation); "
+                      "per-launch figures are averages over the launches of a factorisation" % launches,
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-            "traffic": traffic,
-            "avg_ms": potrf_ms,
-            "flops_per_launch": flops,
+            "traffic": None if traffic is None else traffic / launches,
+            "avg_ms": potrf_ms / launches,
+            "flops_per_launch": flops / launches,
+            "launches_per_factorisation": launches,
+            "ms_per_factorisation": potrf_ms,
+            "flops_per_factorisation": flops,
+            "traffic_per_factorisation": traffic,
         },
     }
     h.close()
