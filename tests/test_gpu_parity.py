@@ -276,6 +276,26 @@ def test_update_slots_in_memory_match_pool(name):
         assert np.array_equal(a, b)
 
 
+def test_solve_one_column_blocks_match_wide_blocks():
+    """Storage blocks of one column (3000 of them) leave the block walk of the
+    inverse-by-solves kernel without room for its descriptor table in LDS, so it
+    takes the generic kernel; the solve must agree with the default 32-column
+    blocks."""
+    prob = sdpgen.maxcut_band(3000, 3, 0.7, 3)
+    from paper_1310_6919_amd.sdpc import sdpc_analyze
+    info = sdpc_analyze(prob, block_width=1)[0]
+    assert info["nblocks"] == 3000
+    res = []
+    for bw in (1, 32):
+        h = _create(prob, block_width=bw)
+        r = h.sdpc_solve()
+        assert r["status"] == 0, r
+        res.append(r)
+        h.close()
+    o1, o32 = [(r["pobj"] + r["dobj"]) / 2 for r in res]
+    assert abs(o1 - o32) <= 1e-7 * max(1.0, abs(o32))
+
+
 def test_solve_cycles_closed_form():
     for n in (5, 8, 13):
         e = sdpgen.cycle_graph(n)
