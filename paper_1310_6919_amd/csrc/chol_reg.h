@@ -59,6 +59,42 @@ __device__ inline void elim_step_bcast(double (&a)[32], double l, int k, int c0)
     }
 }
 
+// Right-looking elimination of 32 columns held one row per lane, a[k] = A(lane,
+// c0 + k), pivot k in lane c0 + k; lanes above the pivot get zero multipliers and
+// row c0 + k gets sqrt(d).  A pivot that is not positive and finite leaves a NaN
+// (or 0 * inf) on the diagonal.  The arithmetic and its order are those of one
+// elim_step_bcast per column, but the bulk multipliers are broadcast through LDS:
+// each step every lane stores its multiplier to Wl (64 doubles, 16-byte aligned,
+// private to the wave) and reads back the ones it needs from uniform addresses.  A
+// wave's LDS operations complete in order, so no wait separates the store from the
+// reads.  Column k + 1 is updated first (its multiplier by readlane) and the next
+// pivot's 1/sqrt is formed while the reads are in flight.  Fewer issue slots than
+// readlanes for every multiplier (a wave alone on its SIMD is issue-bound there),
+// at the cost of registers for the values in flight.
+__device__ inline void elim32_lds(double (&a)[32], int c0, double *Wl) {
+    const int lane = threadIdx.x % 64;
+    double inv = rsqrt_newton(lane_bcast(a[0], c0));
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        __builtin_amdgcn_sched_barrier(0);
+        const double l = (lane >= c0 + k) ? a[k] * inv : 0.0;
+        a[k] = l;
+        if (k + 1 < 32) {
+            Wl[(lane - c0) & 63] = l;   // every lane: no branch
+            a[k + 1] = fma(-l, lane_bcast(l, c0 + k + 1), a[k + 1]);
+            double lj[32];
+#pragma unroll
+            for (int j = k + 2; j < 32; ++j) lj[j] = Wl[j];
+            __builtin_amdgcn_sched_barrier(0);
+            inv = rsqrt_newton(lane_bcast(a[k + 1], c0 + k + 1));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = k + 2; j < 32; ++j) a[j] = fma(-l, lj[j], a[j]);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int NR, int NC>
 struct TileLds {
     double col[2][NR];   // column k of the working matrix (unscaled), rows 0..NR-1

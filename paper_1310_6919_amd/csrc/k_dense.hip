@@ -3,15 +3,16 @@
 //
 // Right-looking, 64-wide column blocks, one fused launch per block column s:
 //   workgroups 0..nt-1   tile rows s .. of column block s.  Each applies the
-//                        pending panel s-1 to the diagonal tile and factorises it
-//                        in one wave (lane = row, pivot column broadcast with
-//                        readlane).  Workgroup 0 stores R_ss and reports a failed
-//                        pivot; every other one also applies panel s-1 to its own
-//                        tile, forms R_ss^{-1} (block inverses, the off-diagonal
-//                        block on the MFMA) and solves X R_ss^T = C as one MFMA
-//                        product.  Repeating the small factorisation in every
-//                        workgroup of the column spares a hand-over through
-//                        memory on the critical path.
+//                        pending panel s-1 to the diagonal tile D and factorises
+//                        it in two 32-column panels, one row per lane (pivot row
+//                        values broadcast by readlane and through LDS), the update
+//                        between the panels on the MFMA.  Workgroup 0 stores R_ss
+//                        and reports a failed pivot; every other one also applies
+//                        panel s-1 to its own tile C, whose rows ride along the
+//                        eliminations (32 per wave) and come out as X = C R_ss^{-T}.
+//                        Repeating the small factorisation in every workgroup of
+//                        the column spares a hand-over through memory on the
+//                        critical path.
 //   the others           apply panel s-1 to every lower tile of the column blocks
 //                        s+1 .. (the bulk of the trailing update), overlapping the
 //                        diagonal factorisations of the same launch.
@@ -107,65 +108,6 @@ __device__ inline void flag_release(int *flag, int epoch) {
     __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Right-looking elimination of 32 columns held one row per lane (a[k] = A(lane,
-// C0 + k)); pivot k sits in lane C0 + k and reaches the other lanes, with the
-// scaled column, through readlane: no LDS, no barrier.  Lanes above the pivot get
-// zero multipliers.  A pivot that is not positive and finite leaves a NaN on the
-// diagonal of L (1/sqrt of it is NaN or makes 0 * inf), so the caller checks the
-// diagonal afterwards instead of testing every pivot inside the chain.
-template <int C0>
-__device__ inline void panel32_wave(double (&a)[32]) {
-    const int lane = threadIdx.x % 64;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const double d = lane_bcast(a[k], C0 + k);
-        const double inv = rsqrt_newton(d);
-        const double l = (lane >= C0 + k) ? a[k] * inv : 0.0;   // row C0 + k gets sqrt(d)
-        a[k] = l;
-        elim_step_bcast(a, l, k, C0);
-    }
-}
-
-// Cholesky of a 64 x 64 matrix held one row per lane by one wave, in two 32-column
-// panels: lo[k] = A(lane, k), hi[k] = A(lane, 32 + k) (lower part used; the upper
-// part ends meaningless).  Between the panels, A22 -= L21 L21^T is one 32 x 32 x 32
-// product on the FP64 MFMA through the LDS scratch W (at least 32 x 33 + 32 x 33
-// doubles).
-__device__ inline void potrf64_wave(double (&lo)[32], double (&hi)[32], double *W) {
-    const int lane = threadIdx.x % 64;
-    panel32_wave<0>(lo);
-    constexpr int LW = 33;
-    double *D = W + 32 * LW;
-    if (lane >= 32) {
-#pragma unroll
-        for (int k = 0; k < 32; ++k) W[(lane - 32) * LW + k] = lo[k];   // W = L21, row-major
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's own LDS stores are done
-    // D = W W^T, lower 16 x 16 blocks (0,0), (1,0), (1,1); lane l supplies
-    // X(l % 16, l / 16) and Z(l / 16, l % 16); result element r: D(4 r + l / 16, l % 16)
-    const int li = lane % 16, lk = lane / 16;
-#pragma unroll
-    for (int blk = 0; blk < 3; ++blk) {
-        const int bi = (blk == 0) ? 0 : 1, bj = (blk == 2) ? 1 : 0;
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const double x = W[(16 * bi + li) * LW + 4 * ks + lk];
-            const double z = W[(16 * bj + li) * LW + 4 * ks + lk];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, z, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) D[(16 * bi + 4 * r + lk) * LW + 16 * bj + li] = acc[r];
-    }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    if (lane >= 32) {
-#pragma unroll
-        for (int k = 0; k < 32; ++k)
-            if (k <= lane - 32) hi[k] -= D[(lane - 32) * LW + k];
-    }
-    panel32_wave<32>(hi);
-}
-
 // The factor of diagonal block s (parked column-major in Rscr[s & 1]) into B:
 // rows J0 + i < rows (right-hand-side rows riding along included), columns
 // k < jb, k <= i.
@@ -187,10 +129,10 @@ k_put_diag(double *__restrict__ B, int64_t ldb, int rows, int m, int s, const do
 __global__ void __launch_bounds__(256)
 k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__restrict__ fail,
             double *__restrict__ Rscr) {
-    __shared__ double S[NB * LDS_LD];   // the updated tile, row-major; then the diagonal factor
-    __shared__ double Ai[32 * 33], Ci[32 * 33], Eb[32 * 33];   // blocks of the factor's inverse
-    __shared__ double invd[NB];
-    const int tid = threadIdx.x;
+    __shared__ double S[NB * LDS_LD];    // the updated diagonal tile, row-major; then R(:, 0:32)
+    __shared__ double Cs[NB * LDS_LD];   // the updated panel tile, row-major; then X(:, 0:32)
+    __shared__ __attribute__((aligned(16))) double Wl[3][64];   // multiplier broadcasts, one row per wave
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const TileIdx t;
     const int T_rows = (rows + NB - 1) / NB, T_cols = (m + NB - 1) / NB;
     const int nt = T_rows - s;
@@ -231,11 +173,14 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
         return;
     }
     // column block s, tile row I.  Every workgroup of the column block factorises the
-    // diagonal tile R_ss itself: a panel tile needs R_ss^{-1}, which it then forms in
-    // its own LDS, so no workgroup waits on another; the diagonal workgroup alone
-    // reports a failed pivot and stores R_ss.
+    // diagonal tile D = R_ss R_ss^T itself, so no workgroup waits on another; the
+    // diagonal workgroup alone reports a failed pivot and stores R_ss.  In the others
+    // the 64 rows of the panel tile C ride along the elimination of D as extra rows
+    // (32 per wave), which leaves X = C R_ss^{-T} in them: the two 32-column panels
+    // of the factorisation are the whole solve.
     const int I = s + int(blockIdx.x), I0 = NB * I;
     const bool diag = (I == s);
+    double *Rs = Rscr + (s & 1) * NB * NB;   // R_ss, column-major, until the next launch
     // quadrant tq of a tile of column block s with panel s-1 applied, in the
     // accumulator layout
     auto stage = [&](const TileIdx &tq, int R0, bool lower, double (&c)[2][2][4]) {
@@ -260,225 +205,138 @@ k_chol_step(double *__restrict__ B, int64_t ldb, int m, int rows, int s, int *__
                     for (int r = 0; r < 4; ++r) c[a][b][r] -= acc[a][b][r];
         }
     };
-    auto to_lds = [&](const TileIdx &tq, const double (&c)[2][2][4]) {
+    auto to_lds = [&](const TileIdx &tq, const double (&c)[2][2][4], double *T) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) S[tq.row(a) * LDS_LD + tq.col(b, r)] = c[a][b][r];
+                for (int r = 0; r < 4; ++r) T[tq.row(a) * LDS_LD + tq.col(b, r)] = c[a][b][r];
     };
-    // the updated panel tile (I, s) is formed by waves 1..3 while wave 0 factorises the
-    // diagonal tile, and parked in its own place in B until S is free again; each
-    // thread reads back exactly the entries it wrote
-    auto own_rw = [&](const TileIdx &tq, double (&c)[2][2][4], bool put) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gi = I0 + tq.row(a), gk = tq.col(b, r);
-                    const bool in = gi < rows && gk < jb;
-                    if (put) {
-                        if (in) B[gi + ldb * (J0 + gk)] = c[a][b][r];
-                    } else {
-                        c[a][b][r] = in ? B[gi + ldb * (J0 + gk)] : 0.0;
-                    }
-                }
-    };
-    const int wv = tid >> 6;
-    // quadrants of the panel tile: waves 1..3 their own, wave 1 also quadrant 0
-    {
-        double cd[2][2][4];
-        stage(t, J0, true, cd);
-        to_lds(t, cd);
+    // quadrant q covers rows 32 (q % 2), columns 32 (q / 2).  D: q0, q1, q3 by waves
+    // 0, 1, 2 (q2 lies above the diagonal); C: q3, q2, q0, q1 by waves 0..3
+    if (wv < 3) {
+        double c[2][2][4];
+        const TileIdx tq(wv == 2 ? 3 : wv);
+        stage(tq, J0, true, c);
+        to_lds(tq, c, S);
+    }
+    if (!diag) {
+        double c[2][2][4];
+        const TileIdx tq(wv == 0 ? 3 : (wv == 1 ? 2 : wv - 2));
+        stage(tq, I0, false, c);
+        to_lds(tq, c, Cs);
     }
     __syncthreads();
-    if (tid >= 64 && !diag) {
-        double co[2][2][4];
-        stage(t, I0, false, co);
-        own_rw(t, co, true);
-        if (wv == 1) {
-            const TileIdx t0(0);
-            stage(t0, I0, false, co);
-            own_rw(t0, co, true);
-        }
-    }
-    if (tid < 64) {
-        __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
-        // rows of the tile below the block's own jb rows (right-hand-side rows riding
-        // along the last block) keep their values in the jb active columns: the
-        // elimination then performs their forward substitution
-        const int lane = tid;
-        const bool real = J0 + lane < rows;
-        double lo[32], hi[32];
+    // D as the elimination sees it: rows at or beyond jb, or beyond the matrix, are
+    // identity rows in the columns at and beyond jb; rows below jb that exist keep
+    // their values in the first jb columns (right-hand-side rows riding along the
+    // last block get their forward substitution)
+    auto dsel = [&](int i, int k, double v) -> double {
+        return (J0 + i < rows && k < jb) ? (k <= i ? v : 0.0) : (i == k ? 1.0 : 0.0);
+    };
+    // every pivot of the block must have been positive and finite (a failed one
+    // leaves a NaN on the diagonal); lanes 0..31 of wave w hold pivots r0 + lane
+    auto check_pivots = [&](const double (&a)[32], int r0) {
+        double dg = 0.0;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {   // every load is in bounds; selects afterwards
-            const double v0 = S[lane * LDS_LD + k], v1 = S[lane * LDS_LD + 32 + k];
-            const int k2 = 32 + k;
-            lo[k] = (real && k < jb) ? (k <= lane ? v0 : 0.0) : (lane == k ? 1.0 : 0.0);
-            hi[k] = (real && k2 < jb) ? (k2 <= lane ? v1 : 0.0) : (lane == k2 ? 1.0 : 0.0);
-        }
-        __builtin_amdgcn_s_waitcnt(0xc07f);   // the tile is in registers before S is reused
-        potrf64_wave(lo, hi, S);               // S serves as its scratch
+        for (int k = 0; k < 32; ++k)
+            if (k == lane) dg = a[k];
+        const unsigned long long badm = __ballot(lane < 32 && r0 + lane < jb && !((dg > 0.0) && isfinite(dg)));
+        if (badm != 0ull && lane == 0) atomicCAS(fail, 0, J0 + r0 + __ffsll((long long)badm));
+    };
+    // panel 1 (columns 0..31): lanes 0..31 hold the pivot rows D(0:32, :); lanes
+    // 32..63 ride along with D(32:64, :) (wave 2) or C rows 32 w .. (waves 0, 1)
+    if (wv == 2 || (!diag && wv < 2)) {
+        __builtin_amdgcn_s_setprio(3);   // the chain of the launch: ahead of the bulk waves on this CU
+        const bool crow = wv < 2 && lane >= 32;
+        const int ci = 32 * wv + lane - 32;   // C row of a riding lane
+        const double *src = crow ? Cs + ci * LDS_LD : S + lane * LDS_LD;
+        double a[32];
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
-            S[lane * LDS_LD + k] = lo[k];
-            S[lane * LDS_LD + 32 + k] = hi[k];
+            const double v = src[k];
+            a[k] = crow ? v : dsel(lane, k, v);
         }
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        const double dg = S[lane * LDS_LD + lane];
-        if (diag) {
-            // every pivot of the block must have been positive and finite
-            const unsigned long long badm = __ballot(lane < jb && !((dg > 0.0) && isfinite(dg)));
-            if (badm != 0ull && lane == 0) atomicCAS(fail, 0, J0 + __ffsll((long long)badm));
-        } else {
-            invd[lane] = 1.0 / dg;
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            // inverses of the four 16 x 16 diagonal blocks of R_ss: lane 16 g + j forms
-            // column j of block g by forward substitution (four partial sums per row);
-            // rows beyond the block's jb rows are taken as identity rows.  Blocks 0, 1
-            // are the diagonal of A^{-1} = R(0:32, 0:32)^{-1} (in Ai), blocks 2, 3 that
-            // of C^{-1} = R(32:64, 32:64)^{-1} (in Ci); above them A^{-1} and C^{-1} are zero.
-            const int g = lane >> 4, j = lane & 15, rb = 16 * g;
-            double x[16];
+        elim32_lds(a, 0, Wl[wv]);
+        if (crow) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                double p[4] = {(i == j) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < 32; ++k) Cs[ci * LDS_LD + k] = a[k];   // X(:, 0:32)
+        } else if (wv == 2) {
 #pragma unroll
-                for (int k = 0; k < i; ++k) p[k & 3] = fma(-S[(rb + i) * LDS_LD + rb + k], x[k], p[k & 3]);
-                const double sacc = (p[0] + p[1]) + (p[2] + p[3]);
-                x[i] = (rb + i < jb) ? sacc * invd[rb + i] : ((i == j) ? 1.0 : 0.0);
-            }
-            double *Xo = (g < 2) ? Ai : Ci;
-            const int o = 16 * (g & 1);
+            for (int k = 0; k < 32; ++k) S[lane * LDS_LD + k] = a[k];   // R(:, 0:32)
+            if (diag) {
+                check_pivots(a, 0);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                Xo[(o + i) * 33 + o + j] = x[i];
-                if (o == 0) Xo[i * 33 + 16 + j] = 0.0;
+                for (int k = 0; k < 32; ++k) Rs[lane + NB * k] = a[k];
             }
         }
         __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
-    if (diag) {
-        // R_ss goes to B one launch later: the other workgroups of this launch still
-        // read the diagonal tile.  It waits in Rscr[s & 1]; R_{s-1,s-1} moves to B now.
-        double *Rs = Rscr + (s & 1) * NB * NB;
-        for (int idx = tid; idx < NB * NB; idx += blockDim.x) Rs[idx] = S[(idx % NB) * LDS_LD + idx / NB];
-        if (s >= 1) put_diag(B, ldb, rows, m, s - 1, Rscr);
-        return;
-    }
-    // the lower-left 16 x 16 blocks of A^{-1} and C^{-1}: -D1^{-1} (R10 D0^{-1}) by wave 0
-    // and -D3^{-1} (R32 D2^{-1}) by wave 1, through Eb
-    if (wv < 2) {
-        const int l = tid & 63, li = l & 15, lk = l >> 4;
-        double *Xb = wv ? Ci : Ai;
-        const int r0 = wv ? 32 : 0;   // row / column offset of the 32 x 32 block in R_ss
-        d4 e = d4{0.0, 0.0, 0.0, 0.0};
+    // the right halves lose [R(32:64, 0:32); X(:, 0:32)] R(32:64, 0:32)^T: 16 x 16
+    // output blocks (rb, cb), rows 16 rb of D(32:64, :) (rb < 2) or of C (rb >= 2),
+    // columns 32 + 16 cb; block (0, 1) lies above the diagonal.  Lane l supplies
+    // X(l % 16, l / 16) and Z(l / 16, l % 16); result element r: (4 r + l / 16, l % 16).
+    {
+        const int li = lane & 15, lk = lane >> 4;
+        for (int b = wv; b < 12; b += 4) {
+            const int rb = b >> 1, cb = b & 1;
+            if ((rb == 0 && cb == 1) || (diag && rb >= 2)) continue;   // uniform
+            double *O = (rb < 2) ? S + (32 + 16 * rb) * LDS_LD : Cs + 16 * (rb - 2) * LDS_LD;
+            const double *Z = S + (32 + 16 * cb) * LDS_LD;
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lk;
-            e = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(r0 + 16 + li) * LDS_LD + r0 + k], Xb[k * 33 + li], e, 0, 0,
-                                                     0);
+            for (int ks = 0; ks < 8; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(O[li * LDS_LD + 4 * ks + lk], Z[li * LDS_LD + 4 * ks + lk],
+                                                           acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) O[(4 * r + lk) * LDS_LD + 32 + 16 * cb + li] -= acc[r];
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Eb[(16 * wv + 4 * r + lk) * 33 + li] = e[r];
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        __builtin_amdgcn_wave_barrier();
-        d4 f = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lk;
-            f = __builtin_amdgcn_mfma_f64_16x16x4f64(Xb[(16 + li) * 33 + 16 + k], Eb[(16 * wv + k) * 33 + li], f, 0,
-                                                     0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Xb[(16 + 4 * r + lk) * 33 + li] = -f[r];
     }
     __syncthreads();
-    // R^{-1}(32:64, 0:32) = F = -C^{-1} (R(32:64, 0:32) A^{-1}): two 32 x 32 x 32 products
-    // on the MFMA, wave w forming the 16 x 16 output block (w / 2, w % 2); F replaces
-    // the intermediate in Eb, the panel tile replaces R_ss in S
-    {
-        const int l = tid & 63, li = l & 15, lk = l >> 4;
-        const int bi = wv >> 1, bj = wv & 1;
-        const bool rowok = 32 + 16 * bi + li < jb;
-        d4 e = d4{0.0, 0.0, 0.0, 0.0};
+    // panel 2 (columns 32..63): lanes 0..31 hold the pivot rows D(32:64, 32:64); lanes
+    // 32..63 ride along with C rows 32 w .. (waves 0, 1) or zeros (diagonal workgroup).
+    // Meanwhile waves 2, 3 store X(:, 0:32), or in the diagonal workgroup waves 1..3
+    // move R_{s-1,s-1} from Rscr to B.
+    if (wv == 0 || (!diag && wv == 1)) {
+        __builtin_amdgcn_s_setprio(3);
+        const bool crow = lane >= 32;
+        const int ci = 32 * wv + lane - 32;
+        const double *src = crow ? Cs + (diag ? 0 : ci) * LDS_LD + 32 : S + (32 + lane) * LDS_LD + 32;
+        double a[32];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int k = 4 * ks + lk;
-            const double xa = rowok ? S[(32 + 16 * bi + li) * LDS_LD + k] : 0.0;
-            const double za = Ai[k * 33 + 16 * bj + li];
-            e = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, e, 0, 0, 0);
+        for (int k = 0; k < 32; ++k) {
+            const double v = src[k];
+            a[k] = crow ? (diag ? 0.0 : v) : dsel(32 + lane, 32 + k, v);
         }
+        elim32_lds(a, 0, Wl[wv]);
+        if (diag) {
+            check_pivots(a, 32);
+            if (!crow) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = e[r];
-        __syncthreads();
-        if (wv >= 1) {   // S is free again: the parked panel tile into S
-            double co[2][2][4];
-            own_rw(t, co, false);
-            to_lds(t, co);
-            if (wv == 1) {
-                const TileIdx t0(0);
-                own_rw(t0, co, false);
-                to_lds(t0, co);
+                for (int k = 0; k < 32; ++k) Rs[(32 + lane) + NB * (32 + k)] = a[k];   // R(32:64, 32:64)
             }
-        }
-        d4 f = d4{0.0, 0.0, 0.0, 0.0};
+        } else if (crow) {
+            const int gi = I0 + ci;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int k = 4 * ks + lk;
-            const double xa = Ci[(16 * bi + li) * 33 + k];
-            const double za = Eb[k * 33 + 16 * bj + li];
-            f = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, za, f, 0, 0, 0);
+            for (int k = 0; k < 32; ++k)
+                if (gi < rows && 32 + k < jb) B[gi + ldb * (J0 + 32 + k)] = a[k];   // X(:, 32:64)
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Eb[(16 * bi + 4 * r + lk) * 33 + 16 * bj + li] = -f[r];
+        __builtin_amdgcn_s_setprio(0);
+    } else if (!diag) {
+        for (int idx = tid - 128; idx < NB * 32; idx += 128) {
+            const int r = idx % NB, k = idx / NB;
+            if (I0 + r < rows && k < jb) B[(I0 + r) + ldb * (J0 + k)] = Cs[r * LDS_LD + k];
+        }
+    } else if (s >= 1) {
+        const int Jp = J0 - NB;   // block s-1 is a full 64-wide block
+        const double *Rp = Rscr + ((s - 1) & 1) * NB * NB;
+        for (int idx = tid - 64; idx < NB * NB; idx += 192) {
+            const int i = idx % NB, k = idx / NB;
+            if (Jp + i < rows && k <= i) B[(Jp + i) + ldb * (Jp + k)] = Rp[idx];
+        }
     }
-    __syncthreads();
-    // X = C R_ss^{-T}: R^{-1}(col, k) is A^{-1} (col, k < 32), zero (col < 32 <= k),
-    // F (col >= 32, k < 32) or C^{-1} (col, k >= 32); columns < 32 need k < 32 only
-    d4 acc[2][2];
-    zero_acc(acc);
-    {
-        const int nks = (t.qc == 0) ? 8 : 16;   // uniform per wave
-        double a[2][16], b[2][16];
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int k = 4 * ks + t.lk;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int col = 16 * u + t.li;   // within the wave's 32 columns
-                a[u][ks] = S[(t.qr + 16 * u + t.li) * LDS_LD + k];
-                double rv;
-                if (t.qc == 0) rv = (k < 32) ? Ai[col * 33 + k] : 0.0;
-                else rv = (k < 32) ? Eb[col * 33 + k] : Ci[col * 33 + (k - 32)];
-                b[u][ks] = rv;
-            }
-        }
-#pragma unroll
-        for (int ks = 0; ks < 16; ++ks)
-            if (ks < nks) {
-#pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
-                        acc[ti][tj] =
-                            __builtin_amdgcn_mfma_f64_16x16x4f64(b[tj][ks], a[ti][ks], acc[ti][tj], 0, 0, 0);
-            }
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gi = I0 + t.row(a), k = t.col(b, r);
-                if (gi < rows && k < jb) B[gi + ldb * (J0 + k)] = acc[a][b][r];
-            }
 }
 
 // R^T x = u, R lower (the factor left in B), u read with a stride (row m of B).
