@@ -174,8 +174,10 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
                      double *d_B, int64_t ldb, int32_t factor);
 
 /* Dense FP64 Cholesky B = R R^T in place (lower triangle of a column-major
- * m x m device matrix, ldb >= m), the factorisation used for the SCM
- * (type (i) of Section 3.1).  The strict upper triangle is not referenced.
+ * m x m device matrix, ldb >= m, 0 <= m <= the handle's number of
+ * constraints, whose workspace it uses; SDPC_E_ARG otherwise), the
+ * factorisation used for the SCM (type (i) of Section 3.1).  The strict upper
+ * triangle is not referenced.
  * Returns SDPC_E_NOT_PD (with the pivot in the detail string) if B is not
  * positive definite.  Synchronises. */
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m);

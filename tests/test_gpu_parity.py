@@ -45,7 +45,9 @@ CASES = {
 
 
 # ----------------------------------------------------------------- dense Cholesky
-@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 130, 200, 257])
+# last blocks of every width class: one column, under / at / over half a block (the
+# second 32-column panel empty, exactly full, partly real), full
+@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 96, 97, 100, 128, 130, 200, 257])
 def test_potrf_matches_lapack(m):
     rng = np.random.default_rng(m)
     prob = sdpgen.maxcut_band(300, 3, 1.0, 0)
@@ -62,16 +64,19 @@ def test_potrf_matches_lapack(m):
     h.close()
 
 
-def test_potrf_reports_not_pd():
-    prob = sdpgen.maxcut_band(100, 3, 1.0, 0)
+# the failing pivot in either 32-column panel of a block, in the first block and a
+# later one, and the last pivot of a ragged last block
+@pytest.mark.parametrize("m,piv", [(80, 50), (80, 3), (130, 70), (130, 127), (130, 129)])
+def test_potrf_reports_not_pd(m, piv):
+    prob = sdpgen.maxcut_band(300, 3, 1.0, 0)   # handle sized for m <= 300
     h = _create(prob)
-    A = np.eye(80)
-    A[50, 50] = -1.0
+    A = np.eye(m)
+    A[piv, piv] = -1.0
     Bt = dev(A.T.copy()).T
     from paper_1310_6919_amd import SdpcError
     with pytest.raises(SdpcError) as e:
-        h.sdpc_potrf(Bt, 80)
-    assert "pivot 50" in str(e.value)
+        h.sdpc_potrf(Bt, m)
+    assert f"pivot {piv}" in str(e.value)
     h.close()
 
 
