@@ -49,9 +49,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def workload():
+BAND = "maxcut-band n=m=4000 bandwidth 20 p=0.5 w~U[0,1] seed 0"
+
+
+def workload(name="band4000"):
+    """(problem, create parameters, description) of a named workload.  band4000 is
+    the metric's workload; latticeP is the max-cut SDP over the paper's P x 10
+    lattice graph (MaxCut400 .. MaxCut1200 sizes at P = 400 .. 1200; weights
+    U[0,1], seed 0) in the short-side-first elimination order."""
     import sdpgen
-    return sdpgen.maxcut_band(4000, 20, 0.5, 0)
+    if name == "band4000":
+        return sdpgen.maxcut_band(4000, 20, 0.5, 0), {}, BAND
+    if name.startswith("lattice"):
+        p = int(name[len("lattice"):])
+        prob = sdpgen.maxcut_lattice(p, 10, 0)
+        desc = (f"maxcut-lattice p={p} q=10 (n=m={10 * p}) w~U[0,1] seed 0, "
+                "short-side-first elimination order")
+        return prob, {"user_perm": sdpgen.lattice_short_first_order(p, 10)}, desc
+    raise SystemExit(f"unknown workload {name}")
 
 
 def cpu_baseline(prob, iters):
@@ -92,6 +107,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="band4000",
+                    help="band4000 (the metric's workload) or latticeP, P x 10 lattice max-cut (e.g. lattice400)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "potrf_traffic.json"),
                     help="HBM traffic per factorisation from rocprofv3 counters (json), if present")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -118,10 +135,10 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
-    prob = workload()
+    prob, cparams, desc = workload(args.workload)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = sdpc_create(prob)
+    h = sdpc_create(prob, **cparams)
     torch.cuda.synchronize()
     create_ms = (time.perf_counter() - t0) * 1e3
     log(f"create: {create_ms:.1f} ms")
@@ -153,7 +170,7 @@ def main():
         # counters count only for the kernel source they were taken on
         try:
             rec = json.load(open(args.traffic))
-            if rec.get("source_sha1") == source_sha1(KERNEL_SOURCE):
+            if rec.get("source_sha1") == source_sha1(KERNEL_SOURCE) and rec.get("m", 4000) == m:
                 traffic = rec.get("bytes_per_factorisation")
         except Exception:
             traffic = None
@@ -170,8 +187,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "maxcut-band n=m=4000 bandwidth 20 p=0.5 w~U[0,1] seed 0",
-                   "n": prob.n, "m": m, "gap_tol": 1e-7, "block_width": int(h.params.block_width)},
+        "config": {"workload": desc, "n": prob.n, "m": m, "gap_tol": 1e-7,
+                   "block_width": int(h.params.block_width)},
         "scm_s_per_iter": scm_per_iter,
         "iters": iters[0],
         "objective": (results[-1]["pobj"] + results[-1]["dobj"]) / 2,
@@ -199,7 +216,12 @@ def main():
         },
     }
     h.close()
-    if not args.no_cpu_baseline:
+    if args.workload.startswith("lattice"):
+        # a bipartite graph: the relaxation's optimum is minus the total weight
+        total = float(prob.meta["weights"].sum())
+        out["optimum_closed_form"] = -total
+        out["objective_rel_err"] = abs(out["objective"] + total) / total
+    if not args.no_cpu_baseline and args.workload == "band4000":
         log(f"cpu baseline: {args.cpu_iters} oracle iterations on the same instance ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -205,6 +205,26 @@ def maxcut_band(n: int = 4000, bw: int = 20, p: float = 0.5, seed: int = 0,
                   meta={"bandwidth": bw})
 
 
+def maxcut_lattice(p: int = 400, q: int = 10, seed: int = 0, wlo: float = 0.0, whi: float = 1.0) -> Problem:
+    """Max-cut over the p x q lattice graph of the paper's experiments (Section 4,
+    the max-cut workloads MaxCut400 .. MaxCut1200 take q = 10), in the paper's
+    vertex numbering; the paper states no weights, these are U[wlo, whi].  The
+    lattice is bipartite, so the relaxation's optimum is minus the total weight."""
+    rng = np.random.default_rng(seed)
+    edges = lattice_graph(p, q)
+    w = rng.uniform(wlo, whi, len(edges))
+    return maxcut(p * q, edges, w, name=f"maxcut_lattice_p{p}_q{q}_s{seed}", meta={"p": p, "q": q})
+
+
+def lattice_short_first_order(p: int, q: int) -> np.ndarray:
+    """An elimination order of the p x q lattice (paper's numbering) that walks the
+    short side first: vertex i + j p for j = 0..q-1, then i + 1, and so on.  In that
+    order every edge joins vertices at most q apart, so the chordal extension is a
+    band of width q with cliques of q + 1 vertices.  perm[k] = the vertex
+    eliminated k-th."""
+    return np.array([i + j * p for i in range(p) for j in range(q)], dtype=np.int32)
+
+
 def maxcut_ktree_batch(count: int = 256, seed: int = 0, nlo: int = 50, nhi: int = 800,
                        klo: int = 3, khi: int = 12, drop: float = 0.3) -> List[Problem]:
     rng = np.random.default_rng(seed)

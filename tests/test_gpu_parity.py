@@ -396,3 +396,46 @@ def test_solve_normmin_full_size_matches_golden():
     gz = np.asarray(g["z"])
     assert np.abs(host(z) - gz).max() <= 1e-6 * max(1.0, np.abs(gz).max())
     h.close()
+
+
+# ----------------------------------------------------------------- lattice max-cut workloads
+def test_lattice_solve_matches_mc_oracle():
+    """A small lattice in the short-side-first elimination order (a caller-given
+    order): the whole trajectory against the matrix-completion oracle in the same
+    order, and the optimum against the closed form (minus the total weight)."""
+    p, q = 12, 10
+    prob = sdpgen.maxcut_lattice(p, q, 4)
+    order = sdpgen.lattice_short_first_order(p, q)
+    total = prob.meta["weights"].sum()
+    ref = oracle.mc_pdipm(prob, oracle.Params(), order=order)
+    assert ref["status"] == "optimal"
+    h = _create(prob, user_perm=order)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    assert r["iters"] == ref["iters"]
+    obj = (r["pobj"] + r["dobj"]) / 2
+    assert abs(obj - (ref["pobj"] + ref["dobj"]) / 2) <= 1e-7 * total
+    assert abs(obj + total) <= 2e-7 * total
+    _, _, z = h.sdpc_get_solution()
+    assert np.abs(host(z) - ref["z"]).max() <= 1e-6 * max(1.0, np.abs(ref["z"]).max())
+    h.close()
+    # the natural order (the paper's numbering: a band of width p) reaches the same optimum
+    h = _create(prob)
+    r2 = h.sdpc_solve()
+    assert r2["status"] == 0, r2
+    assert abs((r2["pobj"] + r2["dobj"]) / 2 + total) <= 2e-7 * total
+    h.close()
+
+
+@pytest.mark.parametrize("p", [400, 1200])
+def test_lattice_full_size_closed_form(p):
+    """MaxCut400 and MaxCut1200 sizes (n = m = 4000 and 12000, q = 10): the solve
+    to gap 1e-7 lands on minus the total weight, the optimum of a bipartite graph."""
+    prob = sdpgen.maxcut_lattice(p, 10, 0)
+    total = prob.meta["weights"].sum()
+    h = _create(prob, user_perm=sdpgen.lattice_short_first_order(p, 10))
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    assert r["rel_gap"] <= 1e-7 and r["pinf"] <= 1e-7 and r["dinf"] <= 1e-7
+    assert abs((r["pobj"] + r["dobj"]) / 2 + total) <= 2e-7 * total
+    h.close()
