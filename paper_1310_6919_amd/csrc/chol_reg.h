@@ -1,6 +1,12 @@
-// Register-tiled Cholesky of a small matrix by one 256-thread workgroup, shared by
-// the diagonal blocks of the dense SCM Cholesky, Algorithm 1, the clique-wise
-// step-length test and the supernodal panels of Y = N N^T.
+// Small dense Cholesky factorisations kept in registers.
+//
+// One row per lane, one wave (lane_bcast, elim_step_bcast, elim32_lds): the
+// one-wave sparse factorisations (Y = N N^T and the dual step's candidates, the
+// clique-wise step-length test) and the diagonal blocks of the dense SCM Cholesky.
+//
+// chol_tile: a register-tiled Cholesky by one 256-thread workgroup, shared by
+// Algorithm 1, the clique-wise step-length test for cliques of more than 32
+// members and the tall supernodal panels of Y = N N^T.
 //
 // Thread t owns a TR x TC tile of the (NR x NC) working matrix, NR = (256 / JG) TR,
 // NC = JG TC: rows i0 = TR (t / JG) + [0, TR), columns j0 = TC (t % JG) + [0, TC).
