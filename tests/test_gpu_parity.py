@@ -439,3 +439,30 @@ def test_lattice_full_size_closed_form(p):
     assert r["rel_gap"] <= 1e-7 and r["pinf"] <= 1e-7 and r["dinf"] <= 1e-7
     assert abs((r["pobj"] + r["dobj"]) / 2 + total) <= 2e-7 * total
     h.close()
+
+
+def test_lattice_min_degree_order_solve():
+    """The minimum-degree order (ordering = 1) gives the lattice a bushy elimination
+    tree of many small storage blocks instead of a band: the whole trajectory against
+    the matrix-completion oracle in its own minimum-degree order (the same fill, so
+    the same E), and the optimum against the closed form."""
+    from oracle.symbolic import aggregate_pattern as agg, min_degree_order
+    p, q = 30, 10
+    prob = sdpgen.maxcut_lattice(p, q, 5)
+    total = prob.meta["weights"].sum()
+    rows, cols = agg(prob)
+    ref = oracle.mc_pdipm(prob, oracle.Params(), order=min_degree_order(prob.n, rows, cols))
+    assert ref["status"] == "optimal"
+    from paper_1310_6919_amd.sdpc import sdpc_analyze
+    info = sdpc_analyze(prob, ordering=1)[0]
+    assert info["nblocks"] > prob.n // 8   # far more blocks than the band order's n / 32
+    h = _create(prob, ordering=1)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    assert r["iters"] == ref["iters"]
+    obj = (r["pobj"] + r["dobj"]) / 2
+    assert abs(obj - (ref["pobj"] + ref["dobj"]) / 2) <= 1e-7 * total
+    assert abs(obj + total) <= 2e-7 * total
+    _, _, z = h.sdpc_get_solution()
+    assert np.abs(host(z) - ref["z"]).max() <= 1e-6 * max(1.0, np.abs(ref["z"]).max())
+    h.close()
