@@ -100,6 +100,60 @@ def cpu_baseline(prob, iters):
     }
 
 
+def batch_loop(args):
+    """256 independent max-cut SDPs (n uniform in [50, 800], random k-trees with k in
+    [3, 12] and 30% of the edges dropped, weights U[0,1], seed 0), each created and
+    solved by the plain solver in the reverse insertion order of its k-tree (a
+    perfect elimination order): the reference for a batched solver.  One step is the
+    whole batch, creates included."""
+    import numpy as np
+    import torch
+    import sdpgen
+    from paper_1310_6919_amd import sdpc_create
+    probs = sdpgen.maxcut_ktree_batch(256, 0)
+    times = []
+    t_create = 0.0
+    iters = []
+    for step in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in probs:
+            t1 = time.perf_counter()
+            h = sdpc_create(p, user_perm=np.arange(p.n)[::-1].astype(np.int32))
+            t_create += time.perf_counter() - t1 if step >= args.warmup else 0.0
+            r = h.sdpc_solve()
+            if r["status"] != 0:
+                raise SystemExit(f"solve failed on {p.name}: {r}")
+            if step >= args.warmup:
+                iters.append(r["iters"])
+            h.close()
+        torch.cuda.synchronize()
+        if step >= args.warmup:
+            times.append(time.perf_counter() - t0)
+        log(f"batch pass {step}: {time.perf_counter() - t0:.2f} s")
+    elapsed = sum(times)
+    out = {
+        "metric": "plain per-instance solves of the 256-instance k-tree max-cut batch, gap 1e-7",
+        "value": len(probs) * args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256 max-cut SDPs, n~U[50,800], random k-trees k~U[3,12], 30% edges dropped, "
+                               "w~U[0,1], seed 0, reverse insertion order", "gap_tol": 1e-7},
+        "create_s_per_step": t_create / args.steps,
+        "iters_mean": float(np.mean(iters)),
+        "iters_max": int(max(iters)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +162,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="band4000",
-                    help="band4000 (the metric's workload) or latticeP, P x 10 lattice max-cut (e.g. lattice400)")
+                    help="band4000 (the metric's workload), latticeP (P x 10 lattice max-cut, e.g. lattice400) "
+                         "or ktree256 (256 uneven k-tree max-cut SDPs, one plain solve each)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "potrf_traffic.json"),
                     help="HBM traffic per factorisation from rocprofv3 counters (json), if present")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -135,6 +190,9 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    if args.workload == "ktree256":
+        batch_loop(args)
+        return
     prob, cparams, desc = workload(args.workload)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
