@@ -466,3 +466,22 @@ def test_lattice_min_degree_order_solve():
     _, _, z = h.sdpc_get_solution()
     assert np.abs(host(z) - ref["z"]).max() <= 1e-6 * max(1.0, np.abs(ref["z"]).max())
     h.close()
+
+
+def test_ktree_batch_instance_matches_mc_oracle():
+    """An instance of the 256-instance k-tree max-cut batch (n = 89, k = 12: a bushy
+    elimination tree) in its reverse insertion order, a perfect elimination order:
+    the whole trajectory against the matrix-completion oracle in the same order."""
+    prob = sdpgen.maxcut_ktree_batch(256, 0)[2]
+    order = np.arange(prob.n)[::-1].astype(np.int32)
+    ref = oracle.mc_pdipm(prob, oracle.Params(), order=order)
+    assert ref["status"] == "optimal"
+    h = _create(prob, user_perm=order)
+    r = h.sdpc_solve()
+    assert r["status"] == 0, r
+    assert r["iters"] == ref["iters"]
+    obj, robj = (r["pobj"] + r["dobj"]) / 2, (ref["pobj"] + ref["dobj"]) / 2
+    assert abs(obj - robj) <= 1e-7 * max(1.0, abs(robj))
+    _, _, z = h.sdpc_get_solution()
+    assert np.abs(host(z) - ref["z"]).max() <= 1e-6 * max(1.0, np.abs(ref["z"]).max())
+    h.close()
