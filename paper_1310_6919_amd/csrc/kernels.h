@@ -133,7 +133,7 @@ void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);
 // ---- factorisations (k_factor.hip)
 // Y = N N^T (supernodal); fail[0] = 0 or 1 + the failing block.  U: scratch of
 // d.nU doubles per candidate (pending updates, when they are not kept in LDS); the
-// dual step needs dual_step_candidates(0, ntest) * d.nU of it.
+// dual step needs d.nU times the candidates of its largest round.
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,
                     hipStream_t st);
 // work (doubles) of launch_sn_chol and launch_dual_step; LDS of their one-wave
