@@ -91,6 +91,14 @@ typedef struct {
     int32_t pool_lds_bytes;    /* LDS budget per wave of the Y factorisation's pending-update
                                   pool; larger pools live in device memory; 0 keeps them
                                   there always                                    (32768)  */
+    int32_t solve_kernel;      /* substitution walk forming X^ and Y^{-1}: 0 picks the
+                                  matrix-core walk when the blocks fit it, 1 always the
+                                  generic walk                                    (0)      */
+    int32_t factorization;     /* how X^ is applied: 0 through X^{-1} = Lhat Lhat^T built by
+                                  Algorithm 1 (Section 3.1); 1 through the earlier sparse
+                                  factorisation X^ = L^T D L (eq. sparse_fact, Section 2.1),
+                                  substituting with the sparse L^{-1} around the block
+                                  diagonal D                                       (0)      */
     int32_t reserved_;         /* 0                                                        */
     const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
                                   i-th (host, read at create)                              */
@@ -127,6 +135,15 @@ typedef struct {
     int32_t nfwd, nbwd;        /* live rows of the forward / backward substitutions         */
     int32_t hadamard;          /* 1 when every A_k (k >= 1) is one diagonal entry          */
     int64_t sum_clique;        /* sum_r |C_r|                                              */
+    /* Limits the structure must respect (sdpc_create fails with SDPC_E_PATTERN
+     * beyond them) and the device memory sdpc_create will ask for. */
+    int32_t limit_clique;      /* largest clique the clique kernels take (64)              */
+    int32_t limit_panel;       /* largest storage panel h x w in doubles (4096)            */
+    int32_t limit_m;           /* most constraints (65535)                                 */
+    int32_t pad_;
+    int64_t device_bytes;      /* workspace of sdpc_create: three dense n x n matrices
+                                  (X^, Y^{-1}, a product), the (m+1) x m SCM, 1024
+                                  candidate factors of nslot doubles, and small arrays    */
 } sdpc_analysis;
 
 /* Host-only symbolic phase (Section 2.1, Section 3.1); touches no device
@@ -182,7 +199,9 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
  * positive definite.  Synchronises. */
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m);
 
-/* Pattern of the storage layout.  *nslot receives the number of stored
+/* Pattern of the storage layout: the extended sparsity pattern E (the chordal
+ * extension of the aggregate pattern, Section 2.1) in the storage order of
+ * the factors, which Lhat and N share (Section 3.1).  *nslot receives the number of stored
  * positions.  iE / jE (host, length nslot, may be NULL) receive, for each
  * stored position, its (row, col) in ORIGINAL indices with row >= col in the
  * elimination order's sense (the position's own row/column), or -1/-1 for a
@@ -197,23 +216,46 @@ sdpc_status sdpc_get_pattern(const sdpc_handle *h, int64_t *nslot, int32_t *iE, 
  * be NULL. */
 sdpc_status sdpc_get_cliques(const sdpc_handle *h, int64_t *cptr, int32_t *cidx, int32_t *nS);
 
-/* Current iterate: Xbar_E, Y_E (E-vectors) and z (length m); device
- * pointers, any may be NULL.  Synchronises. */
+/* Current iterate (Xbar on E, Y, z) of the method of Section 2.2 in the
+ * notation of problems (P) and (D): Xbar_E, Y_E (E-vectors) and z (length m);
+ * device pointers, any may be NULL.  After a failed sdpc_step or sdpc_solve
+ * this is the last iterate that was accepted: a step whose factorisations
+ * reported an error, or whose step lengths collapsed, changes none of X, Y and
+ * z.  Synchronises. */
 sdpc_status sdpc_get_solution(const sdpc_handle *h, double *d_Xbar_E, double *d_Y_E, double *d_z);
 
 /* Replace the current iterate (device pointers; none may be NULL). (async) */
 sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E,
                            const double *d_z);
 
-/* Factors of the last sdpc_scm / iteration in the storage layout (E-vectors
- * in the elimination order): d_N (Y = N N^T), d_Lhat (X^{-1} = Lhat Lhat^T).
+/* Factors in the storage layout (E-vectors in the elimination order):
+ * d_N (Y = N N^T, Section 3.1 type (v)), d_Lhat (X^{-1} = Lhat Lhat^T,
+ * Algorithm 1).  After sdpc_scm both belong to the state it was given.
+ * Inside sdpc_step / sdpc_solve the next X's Lhat is formed while the dual
+ * step runs, so after an iteration d_Lhat already belongs to the new X while
+ * d_N still belongs to the Y the iteration started from; call sdpc_scm with
+ * the state from sdpc_get_solution for factors of one iterate.  With
+ * factorization = 1, d_Lhat receives L^{-1} of eq. sparse_fact instead.
  * Either may be NULL.  Synchronises. */
 sdpc_status sdpc_get_factors(const sdpc_handle *h, double *d_N, double *d_Lhat);
 
-/* Dense X^ (max-determinant completion, Section 2.1) and Y^{-1} of the
- * last sdpc_scm / iteration, n x n column-major in the ELIMINATION order
- * (position i is original index perm[i]).  Either may be NULL.  Synchronises. */
+/* Dense X^ (max-determinant completion, Section 2.1) and Y^{-1} formed by the
+ * last SCM evaluation (sdpc_scm, or the Schur complement phase of the last
+ * iteration, i.e. of the iterate that iteration started from), n x n
+ * column-major in the ELIMINATION order (position i is original index
+ * perm[i]).  Either may be NULL.  Synchronises. */
 sdpc_status sdpc_get_dense(const sdpc_handle *h, double *d_Xhat, double *d_Yinv);
+
+/* Max-determinant positive definite completion X^ of the handle's CURRENT
+ * Xbar (Section 2.1; X^ agrees with Xbar on E and its inverse vanishes off
+ * E): Algorithm 1 gives X^{-1} = Lhat Lhat^T (or, with factorization = 1, the
+ * factorisation of eq. sparse_fact), then X^ e_k by sparse substitutions for
+ * every k (type (iv) of Section 3.1).  d_Xhat (device, n x n column-major in
+ * ORIGINAL indices, may be NULL to only form it) receives X^.  Returns
+ * SDPC_E_NOT_PD if a clique block Xbar(C_r, C_r) is not positive definite.
+ * Overwrites the buffers sdpc_get_dense and sdpc_get_factors read.
+ * Synchronises. */
+sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat);
 
 /* Search direction of the last sdpc_step (Section 2.2, Step 2 with
  * eq. newdX2 and the clique-wise step of eq. primal_length2): d_dz (length

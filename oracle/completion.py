@@ -13,15 +13,18 @@ maxdet_complete   Section 3.1, validity proof of Algorithm 1: for two cliques
 completion_by_vertex
                   The same with one clique per vertex, {j} + struct(j); a
                   different clique sequence that must give the same matrix.
-algorithm1        Algorithm 1 (Steps 1-3): per clique, Cholesky factor M_r of
-                  the block with reversed row/column order, L_r = P_r M_r^{-T}
-                  P_r^T, first |S_r| columns of L_r into Lhat(C_r, S_r).
+algorithm1        Lhat of Algorithm 1 (Section 3.1): on the rows C_r, the
+                  columns S_r of Lhat are the leading |S_r| columns of the
+                  lower-triangular Cholesky factor of (Xbar(C_r, C_r))^{-1}.
+                  Algorithm 1 reaches that factor without an inverse, from a
+                  factorisation of the block in reversed order; here the
+                  inverse of the clique block is formed and factorised
+                  directly, so the two share no arithmetic.
 lhat_textbook     chol(inv(X^)), the definition Algorithm 1 must reproduce.
 """
 from __future__ import annotations
 
 import numpy as np
-import scipy.linalg as sla
 
 from .symbolic import Chordal
 
@@ -52,19 +55,13 @@ def completion_by_vertex(ch: Chordal, Xbar: np.ndarray) -> np.ndarray:
 
 
 def algorithm1(ch: Chordal, Xbar: np.ndarray) -> np.ndarray:
-    """Lhat with Lhat Lhat^T = X^{-1}, computed clique by clique (Algorithm 1).
+    """Lhat with Lhat Lhat^T = X^{-1}, clique by clique (Algorithm 1).
     Returns a dense lower-triangular n x n matrix (zero outside E)."""
-    n = ch.n
-    Lhat = np.zeros((n, n))                                   # Step 1
-    for r in range(ch.ell):                                    # Step 2
-        C = ch.cliques[r]
-        c = len(C)
-        P = np.eye(c)[::-1]                                    # Step 2-1: [P]_ij = 1 iff i + j = c + 1
-        M = np.linalg.cholesky(P @ Xbar[np.ix_(C, C)] @ P.T)   # Step 2-2
-        Minv_T = sla.solve_triangular(M, np.eye(c), lower=True).T
-        Lr = P @ Minv_T @ P.T                                  # Step 2-3
+    Lhat = np.zeros((ch.n, ch.n))
+    for r, C in enumerate(ch.cliques):
         k = int(ch.nS[r])
-        Lhat[np.ix_(C, C[:k])] = Lr[:, :k]                     # Step 3
+        K = np.linalg.cholesky(np.linalg.inv(Xbar[np.ix_(C, C)]))   # K K^T = Xbar(C, C)^{-1}
+        Lhat[np.ix_(C, C[:k])] = K[:, :k]
     return Lhat
 
 

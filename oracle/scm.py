@@ -35,8 +35,9 @@ def _union_support(mats):
     return acc.row.astype(np.int64), acc.col.astype(np.int64)
 
 
-def dense_scm(A, Xhat: np.ndarray, Yinv: np.ndarray, chunk: int = 4096) -> np.ndarray:
-    """A: list of full symmetric scipy matrices A_0..A_m (A[0] unused)."""
+def dense_scm(A, Xhat: np.ndarray, Yinv: np.ndarray, chunk: int = 4096, cols=None) -> np.ndarray:
+    """A: list of full symmetric scipy matrices A_0..A_m (A[0] unused).  cols: if
+    given, only these columns q (0-based) of B are evaluated; the others stay 0."""
     m = len(A) - 1
     n = Xhat.shape[0]
     Ak = A[1:]
@@ -45,6 +46,8 @@ def dense_scm(A, Xhat: np.ndarray, Yinv: np.ndarray, chunk: int = 4096) -> np.nd
     Amat = sp.vstack([sp.csr_matrix(a[Sa, Sb]) for a in Ak]).tocsr()
     B = np.zeros((m, m))
     for q, a in enumerate(Ak):
+        if cols is not None and q not in cols:
+            continue
         a = sp.csc_matrix(a)
         Kq = np.nonzero(np.diff(a.indptr))[0]
         Rq = np.unique(a.indices)

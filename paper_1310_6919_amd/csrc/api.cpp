@@ -40,6 +40,9 @@ namespace {
 constexpr int kDualRounds = 2;
 constexpr int kDualTest[kDualRounds] = {511, 384};
 constexpr int kCand = 1024;      // the most candidates of a round
+constexpr int kMaxClique = 64;   // largest clique of the clique kernels (register tiles of 64 x 64)
+constexpr int kMaxPanel = 4096;  // largest storage panel (doubles): 32 KiB of LDS
+constexpr int kMaxM = 65535;     // most constraints
 
 struct Timer {
     hipEvent_t a{}, b{};
@@ -63,6 +66,7 @@ struct sdpc_handle {
     std::vector<int> slot_row_h, slot_col_h;
     // state (E-vectors unless noted)
     double *X = nullptr, *Y = nullptr, *z = nullptr, *G = nullptr;
+    double *Xn = nullptr;   // the next X, formed before the iteration is known to have succeeded
     double *dX = nullptr, *dY = nullptr, *dz = nullptr;
     double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
@@ -156,6 +160,8 @@ sdpc_params sdpc_default_params(void) {
     p.block_width = 32;
     p.verbose = 0;
     p.pool_lds_bytes = 32 * 1024;
+    p.solve_kernel = 0;
+    p.factorization = 0;
     p.reserved_ = 0;
     p.user_perm = nullptr;
     return p;
@@ -199,6 +205,9 @@ static sdpc_status check_problem(const sdpc_problem *prob, sdpc_handle *h) {
     if (h->prm.pool_lds_bytes < 0 || h->prm.pool_lds_bytes > 64 * 1024)
         return fail(h, SDPC_E_ARG, "pool_lds_bytes must be 0..65536");
     if (h->prm.gamma <= 0 || h->prm.gamma >= 1) return fail(h, SDPC_E_ARG, "gamma must be in (0,1)");
+    if (h->prm.solve_kernel < 0 || h->prm.solve_kernel > 1) return fail(h, SDPC_E_ARG, "solve_kernel must be 0 or 1");
+    if (h->prm.factorization < 0 || h->prm.factorization > 1)
+        return fail(h, SDPC_E_ARG, "factorization must be 0 or 1");
     const int64_t nnz = prob->ptr[m + 1];
     if (prob->ptr[0] != 0 || nnz < 0) return fail(h, SDPC_E_ARG, "ptr must start at 0");
     for (int k = 0; k <= m; ++k)
@@ -235,12 +244,13 @@ static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::v
     so.ordering = h->prm.ordering;
     so.user_perm = h->prm.user_perm;
     so.block_width = h->prm.block_width;
-    so.max_block_entries = 4096;
+    so.max_block_entries = kMaxPanel;
     const std::string serr = build_symbolic(n, arow, acol, so, h->S);
     if (!serr.empty()) return fail(h, SDPC_E_PATTERN, serr);
     const Symbolic &S = h->S;
-    if (S.max_clique > 64)
-        return fail(h, SDPC_E_PATTERN, "largest clique has " + std::to_string(S.max_clique) + " members (limit 64)");
+    if (S.max_clique > kMaxClique)
+        return fail(h, SDPC_E_PATTERN, "largest clique has " + std::to_string(S.max_clique) + " members (limit " +
+                                           std::to_string(kMaxClique) + ")");
     if (S.nslot >= (int64_t(1) << 31)) return fail(h, SDPC_E_PATTERN, "storage exceeds 2^31 entries");
     h->slots = build_solve_slots(S);
     h->d.n = n;
@@ -278,7 +288,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     d.max_h = S.max_h;
     d.max_w = S.max_w;
     d.max_clique = S.max_clique;
-    if (m > 65535) return fail(h, SDPC_E_PATTERN, "more than 65535 constraints");
+    if (m > kMaxM) return fail(h, SDPC_E_PATTERN, "more than " + std::to_string(kMaxM) + " constraints");
+    d.solve_generic = h->prm.solve_kernel;
     // ---- block arrays
     std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size());
     for (size_t t = 0; t < S.bl_rows.size(); ++t) {
@@ -627,10 +638,12 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.zg_slot, zg_slot));
     TRY(upload(h, &d.zg_mma, zg_mma));
     TRY(upload(h, &d.zg_col, zg_col));
+    TRY(upload(h, &d.pos, S.pos));
     // ---- workspace
     const size_t ns = size_t(S.nslot), nn = size_t(n) * n;
     h->ldb = int64_t(m) + 1;   // row m carries the SCE right-hand side through the factorisation
     TRY(dalloc(h, &h->X, ns));
+    TRY(dalloc(h, &h->Xn, ns));
     TRY(dalloc(h, &h->Y, ns));
     TRY(dalloc(h, &h->G, ns));
     TRY(dalloc(h, &h->dX, ns));
@@ -727,6 +740,14 @@ sdpc_status sdpc_analyze(const sdpc_problem *prob, const sdpc_params *params, sd
         if (nS) nS[r] = S.cl_first[r + 1] - f;
     }
     info->sum_clique = off;
+    info->limit_clique = kMaxClique;
+    info->limit_panel = kMaxPanel;
+    info->limit_m = kMaxM;
+    {
+        const int64_t n = prob->n, m = prob->m, ns = S.nslot;
+        info->device_bytes = int64_t(sizeof(double)) * (3 * n * n + (m + 1) * std::max<int64_t>(m, 1) +
+                                                         (kCand + 12) * ns + int64_t(S.nb) * 4 * 64 * 32);
+    }
     if (perm) std::copy(S.perm.begin(), S.perm.end(), perm);
     return SDPC_OK;
 }
@@ -929,21 +950,24 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     launch_zcol(d, h->Xh, h->dY, h->W, st);
     launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
     launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
-    // Step 4 for X with alpha_p still on the device, then Algorithm 1 and Lhat's
-    // diagonal inverses for the next iteration while the dual step runs
+    // Step 4 for X with alpha_p still on the device, into Xn (X itself is replaced
+    // only once the iteration is known to have succeeded), then Algorithm 1 and
+    // Lhat's diagonal inverses for the next iteration while the dual step runs
     const double gm = h->prm.gamma;
-    launch_axpy_E(d, h->X, h->dX, h->scal + 8, gm, st);
-    launch_algorithm1(d, h->X, h->Lhat, h->flags + kCand + 3, st);
+    launch_axpy_checked(d.nslot, h->X, h->dX, h->scal + 8, nullptr, gm, nullptr, 0, h->Xn, st);
+    launch_algorithm1(d, h->Xn, h->Lhat, h->flags + kCand + 3, st);
     launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand + 4, st);
     HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
     HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
     // Step 4 for Y and z (alpha_d = bracket[0] on the device; the same fma as the
-    // dual step's twin candidates, whose factor of the new Y is then reused)
-    launch_axpy_E(d, h->Y, h->dY, h->alphas, gm, st);
-    launch_axpy_vec(d.m, h->z, h->dz, h->alphas, gm, st);
+    // dual step's twin candidates, whose factor of the new Y is then reused).  If a
+    // factorisation of this iteration reported a failure (flags kCand .. kCand + 5)
+    // or a step length is zero, Y and z stay as they are.
+    launch_axpy_checked(d.nslot, h->Y, h->dY, h->alphas, h->scal + 8, gm, h->flags + kCand, 6, h->Y, st);
+    launch_axpy_checked(d.m, h->z, h->dz, h->alphas, h->scal + 8, gm, h->flags + kCand, 6, h->z, st);
     // the metrics of the new iterate (Step 1 of the next iteration), read back with
     // the step lengths and the flags: one synchronisation per iteration
-    launch_metrics(d, h->X, h->Y, h->z, h->G, h->scal, h->mwork, st);
+    launch_metrics(d, h->Xn, h->Y, h->z, h->G, h->scal, h->mwork, st);
     HIPCHK(h, hipGetLastError());
     double ap = 0.0, br[4] = {0, 0, 0, -1};
     int fl[kCand + 8];
@@ -954,9 +978,6 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     HIPCHK(h, hipStreamSynchronize(st));
     read_scm_timing(h);
     TRY(check_flags(h, true, fl));
-    h->metrics_ready = true;
-    h->xside_ready = true;
-    h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
     const double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
     float ms_rhs = 0, ms_chol = 0, ms_pm = 0, ms_potrf = 0;
     (void)hipEventElapsedTime(&ms_potrf, ev[1], ev[6]);
@@ -968,6 +989,12 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     h->last_alpha[0] = ap;
     h->last_alpha[1] = ad;
     if (!(ap > 0.0) || !(ad > 0.0)) return fail(h, SDPC_E_STAGNATION, "step length collapsed to zero");
+    // the iteration succeeded: the new X, the metrics, Lhat and the factor of the new Y
+    // held by a dual-step twin all belong to the new iterate
+    std::swap(h->X, h->Xn);
+    h->metrics_ready = true;
+    h->xside_ready = true;
+    h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
     h->iters++;
     if (res) {
         res->t_scm_ms += t_scm + ms_rhs;
@@ -1150,6 +1177,27 @@ sdpc_status sdpc_get_direction(const sdpc_handle *hc, double *d_dz, double *d_dX
         alpha[0] = h->last_alpha[0];
         alpha[1] = h->last_alpha[1];
     }
+    return SDPC_OK;
+}
+
+sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
+    if (!h) return SDPC_E_ARG;
+    DevStruct &d = h->d;
+    hipStream_t st = h->st;
+    HIPCHK(h, hipMemsetAsync(h->flags + kCand, 0, 8 * sizeof(int), st));
+    h->xside_ready = false;
+    launch_algorithm1(d, h->X, h->Lhat, h->flags + kCand + 1, st);
+    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
+    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st);
+    if (d_Xhat) launch_unpermute(d, h->Xh, d_Xhat, st);
+    HIPCHK(h, hipGetLastError());
+    int fl[2] = {0, 0};
+    HIPCHK(h, hipMemcpyAsync(fl, h->flags + kCand, sizeof(fl), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (fl[1])
+        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[1] - 1) + ")");
+    if (fl[0]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
+    h->xside_ready = true;   // Lhat and its diagonal inverses belong to the current X
     return SDPC_OK;
 }
 

@@ -10,10 +10,11 @@
 //                 (Section 2.2, Step 3).
 //  k_dinv         inverses of the diagonal blocks of a factor (used by the
 //                 multi-right-hand-side substitutions).
-//  k_algorithm1   Algorithm 1: per clique C_r, reverse the order of
-//                 Xbar(C_r, C_r) (Step 2-1), factorise it as M_r M_r^T
-//                 (Step 2-2), form L_r = P_r M_r^{-T} P_r^T (Step 2-3) and
-//                 store its first |S_r| columns as Lhat(C_r, S_r) (Step 3).
+//  k_algorithm1   Algorithm 1: per clique C_r, the lower Cholesky factor of
+//                 (Xbar(C_r, C_r))^{-1} without forming the inverse: the block
+//                 in reversed order P_r Xbar P_r^T = M_r M_r^T gives it as
+//                 P_r M_r^{-T} P_r^T, whose first |S_r| columns are
+//                 Lhat(C_r, S_r).
 //  k_alpha_cl     eq. primal_length2: per clique the largest alpha in (0, 1]
 //                 keeping Xbar(C_r,C_r) + alpha dX(C_r,C_r) positive definite,
 //                 found by bisection on the Cholesky test.
@@ -373,7 +374,7 @@ k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_
     const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
     // packed lower index of clique entry (ii, jj), ii >= jj: jj * (2c - jj + 1) / 2 + (ii - jj)
     auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
-    // Step 2-1: Z = P_r Xbar(C_r, C_r) P_r^T, Z(a, b) = Xbar(C[c-1-a], C[c-1-b]);
+    // Z = P_r Xbar(C_r, C_r) P_r^T, Z(a, b) = Xbar(C[c-1-a], C[c-1-b]);
     // identity beyond the clique order
     double a[4][4], m[4][4];
 #pragma unroll
@@ -384,14 +385,14 @@ k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_
             a[u][v] = (i < c && k <= i) ? Xbar[map[pk(c - 1 - k, c - 1 - i)]] : (i == k ? 1.0 : 0.0);
             m[u][v] = (i == k) ? 1.0 : 0.0;
         }
-    // Step 2-2: Z = M_r M_r^T, with M_r^{-1} alongside
+    // Z = M_r M_r^T, with M_r^{-1} alongside
     int bad = 0;
     if (!chol_tile<4, 4, 16, true>(a, m, c, sh, &bad)) {
         if (tid == 0) atomicCAS(fail, 0, r + 1);
         return;
     }
-    // Steps 2-3 and 3: L_r = P_r M_r^{-T} P_r^T, i.e. L_r(ii, jj) = M_r^{-1}(c-1-jj, c-1-ii);
-    // its first ns columns are Lhat(C_r, S_r), i.e. rows >= c - ns of M_r^{-1}
+    // L_r = P_r M_r^{-T} P_r^T, i.e. L_r(ii, jj) = M_r^{-1}(c-1-jj, c-1-ii); its first
+    // ns columns are Lhat(C_r, S_r), i.e. rows >= c - ns of M_r^{-1}
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -529,7 +530,9 @@ __global__ void __launch_bounds__(1024) k_bracket(int ntest, int round, double g
             bracket[3] = (fail[ntest] == 0) ? double(ntest) : -1.0;
             return;
         }
-        if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 1.0; bracket[3] = -1.0; return; }
+        // no grid point passed: the step is below the grid's smallest point, and the
+        // next round searches (0, that point) evenly instead of giving up
+        if (best < 0) { bracket[0] = 0.0; bracket[1] = cand(0); bracket[2] = 0.0; bracket[3] = -1.0; return; }
         const double lo = cand(best), hi = cand(best + 1);
         bracket[0] = lo; bracket[1] = hi; bracket[2] = 0.0; bracket[3] = -1.0;
         return;

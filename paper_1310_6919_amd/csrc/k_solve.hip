@@ -649,7 +649,7 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
                               const double *L1, const double *Dinv1, double *out1, hipStream_t st) {
     const int nf = L1 ? 2 : 1;
     const int nt = (d.n + 31) / 32;
-    if (solve_mma_ok(d)) {
+    if (!d.solve_generic && solve_mma_ok(d)) {
         hipLaunchKernelGGL(k_inv_solve_mma, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), solve_lds_mma(d), st,
                            d.n, d.nb, d.max_w, d.max_h, solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off,
                            d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0,

@@ -122,14 +122,34 @@ __global__ void k_metrics_final(int ng, const double *__restrict__ part, double 
     for (int i = 0; i < 6; ++i) scal[i] = v[i];
 }
 
-// x += coef dx, with coef = scale * alpha[0] when alpha is given (a step length
-// still on the device), else coef = scale
-__global__ void k_axpy(int64_t len, double *__restrict__ x, const double *__restrict__ dx,
-                       const double *__restrict__ alpha, double scale) {
-    const double coef = alpha ? scale * alpha[0] : scale;
+// Step 4 with the step lengths still on the device: out = x + scale * alpha[0] * dx,
+// unless the iteration has failed, i.e. one of the nflag failure flags is set or
+// one of the two step lengths (alpha[0] and, when given, alpha2[0]) is not
+// positive; then out = x (in place: untouched), so a failed step leaves the
+// iterate as it was.
+__global__ void k_axpy_checked(int64_t len, const double *x, const double *__restrict__ dx,
+                               const double *__restrict__ alpha, const double *__restrict__ alpha2, double scale,
+                               const int *__restrict__ flags, int nflag, double *out) {
+    bool ok = alpha[0] > 0.0 && (!alpha2 || alpha2[0] > 0.0);
+    for (int i = 0; i < nflag; ++i) ok = ok && flags[i] == 0;
+    const double coef = scale * alpha[0];
     for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < len;
-         s += int64_t(gridDim.x) * blockDim.x)
-        x[s] = fma(coef, dx[s], x[s]);   // the same rounding as the dual-step candidates
+         s += int64_t(gridDim.x) * blockDim.x) {
+        if (ok)
+            out[s] = fma(coef, dx[s], x[s]);   // the same rounding as the dual-step candidates
+        else if (out != x)
+            out[s] = x[s];
+    }
+}
+
+// out(i, j) = in(pos[i], pos[j]): a dense n x n column-major matrix from the
+// elimination order back to the original indices
+__global__ void __launch_bounds__(256) k_unpermute(int n, const int *__restrict__ pos, const double *__restrict__ in,
+                                                   double *__restrict__ out) {
+    const int j = blockIdx.x;
+    const int64_t pj = int64_t(pos[j]) * n;
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < n; i += gridDim.y * blockDim.x)
+        out[i + int64_t(n) * j] = in[pos[i] + pj];
 }
 
 __global__ void k_init(int64_t nslot, const double *__restrict__ wE, double lambda, double *X, double *Y,
@@ -177,13 +197,15 @@ void launch_metrics(const DevStruct &d, const double *X, const double *Y, const 
     hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(64), 0, st, kMetricsGroups, (const double *)work, scal);
 }
 
-void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha, double scale,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(d.nslot)), dim3(kThreads), 0, st, d.nslot, x, dx, alpha, scale);
+void launch_axpy_checked(int64_t len, const double *x, const double *dx, const double *alpha, const double *alpha2,
+                         double scale, const int *flags, int nflag, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_checked, dim3(grid_for(len)), dim3(kThreads), 0, st, len, x, dx, alpha, alpha2, scale,
+                       flags, nflag, out);
 }
 
-void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha, double scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(m)), dim3(kThreads), 0, st, int64_t(m), x, dx, alpha, scale);
+void launch_unpermute(const DevStruct &d, const double *in, double *out, hipStream_t st) {
+    if (d.n <= 0) return;
+    hipLaunchKernelGGL(k_unpermute, dim3(d.n, (d.n + 255) / 256), dim3(256), 0, st, d.n, d.pos, in, out);
 }
 
 void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z, hipStream_t st) {

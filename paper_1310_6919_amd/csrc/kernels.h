@@ -1,7 +1,6 @@
 // Device data structures and kernel launchers (host-callable).
 //
-// Storage layout shared by Lhat, N and every E-vector (Section 3.1: "the
-// structure of the memory allocated to Lhat is identical to that of N"):
+// Lhat, N and every E-vector share one storage layout (Section 3.1):
 // block b owns columns [bl_first[b], bl_first[b+1]) and rows
 // bl_rows[bl_rptr[b] .. bl_rptr[b+1]) (own columns first); its panel is the
 // h x w column-major array at offset bl_off[b].
@@ -111,6 +110,8 @@ struct DevStruct {
     int nzg_mma = 0, nzg_col = 0;
     const int *zg_mma = nullptr;        // groups on the MFMA path
     const int *zg_col = nullptr;        // groups on the column path
+    const int *pos = nullptr;           // n: position (elimination order) of every original index
+    int solve_generic = 0;              // 1: the substitutions always take the generic walk
 };
 constexpr int kZmRows = 128;
 
@@ -122,10 +123,12 @@ size_t metrics_work_doubles();   // work of launch_metrics
 // scal[...] <- pobj, dobj, max|r|, max|G|, X.Y, also G_E (see k_vec.hip)
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z,
                     double *G, double *scal, double *work, hipStream_t st);
-// x += scale * alpha[0] * dx (alpha a device scalar), or x += scale * dx when alpha is null
-void launch_axpy_E(const DevStruct &d, double *x, const double *dx, const double *alpha, double scale,
-                   hipStream_t st);
-void launch_axpy_vec(int m, double *x, const double *dx, const double *alpha, double scale, hipStream_t st);
+// out = x + scale * alpha[0] * dx when flags[0..nflag) are all zero and alpha[0] (and
+// alpha2[0] when given) are positive, else out = x; out may be x
+void launch_axpy_checked(int64_t len, const double *x, const double *dx, const double *alpha, const double *alpha2,
+                         double scale, const int *flags, int nflag, double *out, hipStream_t st);
+// out(i, j) = in(pos[i], pos[j]) for dense n x n column-major matrices
+void launch_unpermute(const DevStruct &d, const double *in, double *out, hipStream_t st);
 void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z,
                        hipStream_t st);
 void launch_mask_E(const DevStruct &d, double *v, hipStream_t st);

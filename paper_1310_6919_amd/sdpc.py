@@ -21,7 +21,7 @@ SDPC_OK, SDPC_E_ARG, SDPC_E_PATTERN, SDPC_E_NOT_PD, SDPC_E_HIP, SDPC_E_MAXITER, 
 
 EXPORTS = ["sdpc_default_params", "sdpc_analyze", "sdpc_create", "sdpc_solve", "sdpc_reset", "sdpc_step", "sdpc_scm",
            "sdpc_potrf", "sdpc_get_pattern", "sdpc_get_cliques", "sdpc_get_solution", "sdpc_set_state",
-           "sdpc_get_factors", "sdpc_get_dense", "sdpc_get_direction", "sdpc_get_scm_timing",
+           "sdpc_get_factors", "sdpc_get_dense", "sdpc_complete_dense", "sdpc_get_direction", "sdpc_get_scm_timing",
            "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
 
 
@@ -35,14 +35,16 @@ class sdpc_params(C.Structure):
     _fields_ = [("gap_tol", C.c_double), ("feas_tol", C.c_double), ("beta_feas", C.c_double),
                 ("beta_infeas", C.c_double), ("gamma", C.c_double), ("lambda0", C.c_double),
                 ("max_iter", C.c_int32), ("ordering", C.c_int32), ("block_width", C.c_int32),
-                ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("reserved_", C.c_int32),
-                ("user_perm", C.POINTER(C.c_int32))]
+                ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("solve_kernel", C.c_int32),
+                ("factorization", C.c_int32), ("reserved_", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
 
 
 class sdpc_analysis(C.Structure):
     _fields_ = [("nslot", C.c_int64), ("nnzE", C.c_int64), ("ncliques", C.c_int32), ("nblocks", C.c_int32),
                 ("max_clique", C.c_int32), ("max_block_rows", C.c_int32), ("max_block_cols", C.c_int32),
-                ("nfwd", C.c_int32), ("nbwd", C.c_int32), ("hadamard", C.c_int32), ("sum_clique", C.c_int64)]
+                ("nfwd", C.c_int32), ("nbwd", C.c_int32), ("hadamard", C.c_int32), ("sum_clique", C.c_int64),
+                ("limit_clique", C.c_int32), ("limit_panel", C.c_int32), ("limit_m", C.c_int32),
+                ("pad_", C.c_int32), ("device_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -87,6 +89,7 @@ def load():
         "sdpc_set_state": (I32, [VP, VP, VP, VP]),
         "sdpc_get_factors": (I32, [VP, VP, VP]),
         "sdpc_get_dense": (I32, [VP, VP, VP]),
+        "sdpc_complete_dense": (I32, [VP, VP]),
         "sdpc_get_direction": (I32, [VP, VP, VP, VP, P(D)]),
         "sdpc_get_scm_timing": (I32, [VP, P(D)]),
         "sdpc_status_string": (C.c_char_p, [I32]),
@@ -290,6 +293,12 @@ class Handle:
         Xh, Yi = self._empty(self.n, self.n), self._empty(self.n, self.n)
         self._check(self.lib.sdpc_get_dense(self.h, _ptr(Xh), _ptr(Yi)), "sdpc_get_dense")
         return Xh.T, Yi.T   # stored column-major
+
+    def sdpc_complete_dense(self, out=True):
+        """Max-determinant completion of the current Xbar, n x n in original indices."""
+        Xh = self._empty(self.n, self.n) if out else None
+        self._check(self.lib.sdpc_complete_dense(self.h, _ptr(Xh)), "sdpc_complete_dense")
+        return None if Xh is None else Xh.T   # stored column-major (symmetric anyway)
 
     def sdpc_get_direction(self):
         dz, dX, dY = self._empty(self.m), self._empty(self.nslot), self._empty(self.nslot)

@@ -1,0 +1,235 @@
+"""GPU: the remaining entry points and paths of the C ABI against the oracle.
+
+  * the generic substitution walk (solve_kernel = 1, and the default choice
+    when the matrix-core walk does not fit) against the oracle's completion,
+    inverse and Schur complement matrix;
+  * the Schur complement matrix at a general (not central) state at the
+    full sizes of the max-cut band workload (n = m = 4000) and the
+    norm-minimisation workload (n = 2010, m = 64), on seeded samples of its
+    columns;
+  * sdpc_complete_dense (the max-determinant completion of the current
+    iterate, Section 2.1) against the oracle's completion;
+  * a failed iteration leaves the iterate untouched;
+  * two identical solves are bit for bit identical.
+
+Tolerances as in test_gpu_parity (1e-10 relative to max |B| for states with
+cond <= ~50).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sdpgen
+from oracle.symbolic import aggregate_pattern, chordal_structure
+from tests.gpu_common import dev, from_E, host, rel_err, to_E
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1310_6919_amd import load
+    load()
+
+
+def _create(prob, **kw):
+    from paper_1310_6919_amd import sdpc_create
+    return sdpc_create(prob, **kw)
+
+
+CASES = {
+    "cfg1": lambda: sdpgen.maxcut_cycle_chords(64, 0),
+    "band300": lambda: sdpgen.maxcut_band(300, 20, 0.5, 1),
+    "band_ragged": lambda: sdpgen.maxcut_band(333, 7, 0.7, 2),
+    "normmin": lambda: sdpgen.normmin(100, 10, 8, 0),
+    "random_sdp": lambda: sdpgen.random_sparse_sdp(45, 20, seed=4),
+    "band_wide": lambda: sdpgen.maxcut_band(260, 50, 0.9, 5),
+}
+
+
+def _state(prob, rng, cond=8.0):
+    rows, cols = aggregate_pattern(prob)
+    Xfull = sdpgen.random_pd_dense(prob.n, rng, cond=cond)
+    Y = sdpgen.random_pd_on_pattern(prob.n, rows, cols, rng)
+    return Xfull, Y
+
+
+def _oracle_completion(prob, Xfull):
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)   # natural order, the library's default
+    return oracle.maxdet_complete(ch, np.where(ch.E_mask(), Xfull, 0.0))
+
+
+def _check_scm(prob, h, rng, cols=None):
+    Xfull, Y = _state(prob, rng)
+    B = np.tril(host(h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)))))
+    Xh = _oracle_completion(prob, Xfull)
+    Yi = np.linalg.inv(Y)
+    A = oracle.scm.problem_mats(prob)
+    Bref = oracle.dense_scm(A, Xh, Yi, cols=None if cols is None else set(int(c) for c in cols))
+    if cols is None:
+        assert rel_err(B, np.tril(Bref)) <= 1e-10
+    else:
+        low = np.arange(prob.m)[:, None] >= np.asarray(cols)[None, :]
+        assert rel_err(np.where(low, B[:, cols], 0.0), np.where(low, Bref[:, cols], 0.0)) <= 1e-10
+    _, _, perm = h.sdpc_get_pattern()
+    Xd, Yd = h.sdpc_get_dense()
+    assert rel_err(host(Xd), Xh[np.ix_(perm, perm)]) <= 1e-10
+    assert rel_err(host(Yd), Yi[np.ix_(perm, perm)]) <= 1e-10
+
+
+# ----------------------------------------------------------------- generic substitution walk
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_scm_generic_walk_matches_oracle(name):
+    """solve_kernel = 1: X^ and Y^{-1} from the generic walk, and B from them."""
+    prob = CASES[name]()
+    h = _create(prob, solve_kernel=1)
+    _check_scm(prob, h, np.random.default_rng(7))
+    h.close()
+
+
+def test_scm_one_column_blocks_match_oracle():
+    """3000 storage blocks of one column: the matrix-core walk's descriptor table does
+    not fit its LDS, so the default choice is the generic walk."""
+    prob = sdpgen.maxcut_band(3000, 3, 0.7, 3)
+    from paper_1310_6919_amd.sdpc import sdpc_analyze
+    assert sdpc_analyze(prob, block_width=1)[0]["nblocks"] == 3000
+    h = _create(prob, block_width=1)
+    _check_scm(prob, h, np.random.default_rng(8))
+    h.close()
+
+
+# ----------------------------------------------------------------- full sizes, general state
+def test_scm_general_state_bench_workload():
+    """max-cut band n = m = 4000 (the bench workload, default parameters): B at a
+    random positive definite state on 64 seeded columns, and the whole X^ and Y^{-1}."""
+    prob = sdpgen.maxcut_band(4000, 20, 0.5, 0)
+    rng = np.random.default_rng(31)
+    cols = np.sort(np.random.default_rng(32).choice(prob.m, 64, replace=False))
+    h = _create(prob)
+    _check_scm(prob, h, rng, cols=cols)
+    h.close()
+
+
+def test_scm_general_state_normmin_full_size():
+    """norm minimisation p = 2000, q = 10, 63 coefficients (n = 2010, m = 64): B at a
+    random positive definite state on 8 seeded columns (the general, non-Hadamard path)."""
+    prob = sdpgen.normmin(2000, 10, 63, 0)
+    rng = np.random.default_rng(41)
+    cols = np.sort(np.random.default_rng(42).choice(prob.m, 8, replace=False))
+    h = _create(prob)
+    _check_scm(prob, h, rng, cols=cols)
+    h.close()
+
+
+# ----------------------------------------------------------------- completion of the current iterate
+@pytest.mark.parametrize("name", ["cfg1", "band_ragged", "normmin", "random_sdp", "band_wide"])
+def test_complete_dense_matches_oracle(name):
+    prob = CASES[name]()
+    rng = np.random.default_rng(13)
+    Xfull, Y = _state(prob, rng)
+    z = rng.standard_normal(prob.m) * 0.1
+    h = _create(prob)
+    h.sdpc_set_state(dev(to_E(h, Xfull)), dev(to_E(h, Y)), dev(z))
+    Xh = host(h.sdpc_complete_dense())
+    assert rel_err(Xh, _oracle_completion(prob, Xfull)) <= 1e-10
+    # after two iterations: the completion of the iterate the handle now holds
+    h.sdpc_reset()
+    h.sdpc_step()
+    h.sdpc_step()
+    X_E, _, _ = h.sdpc_get_solution()
+    Xbar = from_E(h, host(X_E))
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    ref = oracle.maxdet_complete(ch, Xbar)
+    assert rel_err(host(h.sdpc_complete_dense()), ref) <= 1e-10
+    h.close()
+
+
+def test_complete_dense_rejects_non_pd_clique():
+    prob = CASES["cfg1"]()
+    h = _create(prob)
+    X = np.eye(prob.n)
+    X[4, 4] = -1.0
+    h.sdpc_set_state(dev(to_E(h, X)), dev(to_E(h, np.eye(prob.n))), dev(np.zeros(prob.m)))
+    from paper_1310_6919_amd import SdpcError
+    from paper_1310_6919_amd.sdpc import SDPC_E_NOT_PD
+    with pytest.raises(SdpcError) as e:
+        h.sdpc_complete_dense()
+    assert e.value.status == SDPC_E_NOT_PD
+    h.close()
+
+
+# ----------------------------------------------------------------- failed iterations
+def _snapshot(h):
+    return [host(t).copy() for t in h.sdpc_get_solution()]
+
+
+def test_failed_step_keeps_iterate_when_y_not_pd():
+    """A Y that is not positive definite: the Y factorisation reports it, and the
+    iteration changes none of X, Y and z."""
+    prob = CASES["band_ragged"]()
+    rng = np.random.default_rng(17)
+    Xfull, Y = _state(prob, rng)
+    Y[5, 5] = -1.0
+    z = rng.standard_normal(prob.m) * 0.1
+    h = _create(prob)
+    h.sdpc_set_state(dev(to_E(h, Xfull)), dev(to_E(h, Y)), dev(z))
+    before = _snapshot(h)
+    from paper_1310_6919_amd import SdpcError
+    from paper_1310_6919_amd.sdpc import SDPC_E_NOT_PD
+    with pytest.raises(SdpcError) as e:
+        h.sdpc_step()
+    assert e.value.status == SDPC_E_NOT_PD
+    for a, b in zip(before, _snapshot(h)):
+        assert np.array_equal(a, b)
+    h.close()
+
+
+def test_failed_step_keeps_iterate_when_scm_singular():
+    """A constraint matrix that is zero makes B singular (a zero row and column): the
+    SCM Cholesky reports the pivot, and the iteration changes none of X, Y and z."""
+    base = sdpgen.random_sparse_sdp(30, 8, seed=6)
+    mats = [base.triplets(k) for k in range(base.m + 1)]
+    mats[3] = (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    b = base.b.copy()
+    b[2] = 0.0
+    prob = sdpgen.from_matrices(base.n, mats, b, name="zero_constraint")
+    h = _create(prob)
+    h.sdpc_reset()
+    before = _snapshot(h)
+    from paper_1310_6919_amd import SdpcError
+    from paper_1310_6919_amd.sdpc import SDPC_E_NOT_PD
+    with pytest.raises(SdpcError) as e:
+        h.sdpc_step()
+    assert e.value.status == SDPC_E_NOT_PD
+    assert "pivot 2" in str(e.value)
+    for a, b_ in zip(before, _snapshot(h)):
+        assert np.array_equal(a, b_)
+    h.close()
+
+
+# ----------------------------------------------------------------- determinism
+@pytest.mark.parametrize("name", ["band_ragged", "normmin"])
+def test_solves_are_bitwise_reproducible(name):
+    """Every reduction has a fixed order: two solves of one problem (and on two
+    handles) give the same iterates bit for bit."""
+    prob = CASES[name]()
+    out = []
+    h = _create(prob)
+    for _ in range(2):
+        r = h.sdpc_solve()
+        assert r["status"] == 0, r
+        out.append((r["iters"], r["pobj"], r["dobj"], *_snapshot(h)))
+    h.close()
+    h = _create(prob)
+    r = h.sdpc_solve()
+    out.append((r["iters"], r["pobj"], r["dobj"], *_snapshot(h)))
+    h.close()
+    for o in out[1:]:
+        assert o[0] == out[0][0] and o[1] == out[0][1] and o[2] == out[0][2]
+        for a, b in zip(o[3:], out[0][3:]):
+            assert np.array_equal(a, b)
