@@ -269,7 +269,28 @@ sdpc_status sdpc_get_direction(const sdpc_handle *h, double *d_dz, double *d_dX_
  * of 5.  Synchronises. */
 sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the dense
+ * FP64 Cholesky of sdpc_potrf, B = R R^T in place on the lower triangle of a
+ * column-major m x m device matrix (ldb >= max(1, m)), without a handle.  It
+ * calls no hipMalloc, hipFree or allocating library routine: its workspace
+ * (64 KiB of parked diagonal factors and a failure flag) is one fixed device
+ * array per GPU, held from the first call on that GPU until the process ends.
+ * Limit: m <= 65535 (SDPC_E_ARG beyond it, with the reason in
+ * sdpc_last_error(NULL)).  All work is enqueued on `stream` (its device is the
+ * one used; NULL: the current device's default stream).
+ * d_info (device, optional): with d_info != NULL the call is asynchronous and
+ * *d_info receives 0, or 1 + the failing pivot if B is not positive definite
+ * (-1 if an internal hand-over wait ran out); with d_info == NULL the call
+ * synchronises the stream and returns SDPC_E_NOT_PD on a failed pivot.
+ * Every call on one GPU shares that GPU's workspace: calls that overlap on one
+ * GPU (other streams, other host threads) race and must be serialised by the
+ * caller. */
+sdpc_status sdpc_potrf_static(double *d_B, int64_t ldb, int32_t m, int32_t *d_info, hipStream_t stream);
+
 const char *sdpc_status_string(sdpc_status s);
+/* Detail of the last error of handle h; with h == NULL, of the last failed
+ * call made without a handle on this host thread. */
 const char *sdpc_last_error(const sdpc_handle *h);
 void sdpc_destroy(sdpc_handle *h);
 

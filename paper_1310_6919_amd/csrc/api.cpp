@@ -94,6 +94,18 @@ struct sdpc_handle {
     int iters = 0;
 };
 
+namespace sdpc {
+
+// detail of the last failed call that has no handle (per host thread)
+std::string &unbound_error() {
+    static thread_local std::string e = "no error";
+    return e;
+}
+
+void set_unbound_error(const std::string &msg) { unbound_error() = msg; }
+
+}  // namespace sdpc
+
 namespace {
 
 sdpc_status fail(sdpc_handle *h, sdpc_status s, const std::string &msg) {
@@ -182,7 +194,7 @@ const char *sdpc_status_string(sdpc_status s) {
     return "unknown status";
 }
 
-const char *sdpc_last_error(const sdpc_handle *h) { return h ? h->err.c_str() : "null handle"; }
+const char *sdpc_last_error(const sdpc_handle *h) { return h ? h->err.c_str() : unbound_error().c_str(); }
 
 void sdpc_destroy(sdpc_handle *h) {
     if (!h) return;

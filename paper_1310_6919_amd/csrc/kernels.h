@@ -8,8 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace sdpc {
+
+// Detail string of the last failed call made without a handle, per host thread
+// (what sdpc_last_error(NULL) returns).
+std::string &unbound_error();
+void set_unbound_error(const std::string &msg);
 
 // Copy count doubles from global memory to LDS, issuing U loads per thread before
 // any LDS store so that the loads overlap instead of waiting one by one.

@@ -22,7 +22,7 @@ SDPC_OK, SDPC_E_ARG, SDPC_E_PATTERN, SDPC_E_NOT_PD, SDPC_E_HIP, SDPC_E_MAXITER, 
 EXPORTS = ["sdpc_default_params", "sdpc_analyze", "sdpc_create", "sdpc_solve", "sdpc_reset", "sdpc_step", "sdpc_scm",
            "sdpc_potrf", "sdpc_get_pattern", "sdpc_get_cliques", "sdpc_get_solution", "sdpc_set_state",
            "sdpc_get_factors", "sdpc_get_dense", "sdpc_complete_dense", "sdpc_get_direction", "sdpc_get_scm_timing",
-           "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
+           "sdpc_potrf_static", "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
 
 
 class sdpc_problem(C.Structure):
@@ -92,6 +92,7 @@ def load():
         "sdpc_complete_dense": (I32, [VP, VP]),
         "sdpc_get_direction": (I32, [VP, VP, VP, VP, P(D)]),
         "sdpc_get_scm_timing": (I32, [VP, P(D)]),
+        "sdpc_potrf_static": (I32, [VP, I64, I32, VP, VP]),
         "sdpc_status_string": (C.c_char_p, [I32]),
         "sdpc_last_error": (C.c_char_p, [VP]),
         "sdpc_destroy": (None, [VP]),
@@ -310,6 +311,23 @@ class Handle:
         ms = (C.c_double * 5)()
         self._check(self.lib.sdpc_get_scm_timing(self.h, ms), "sdpc_get_scm_timing")
         return list(ms)
+
+
+def sdpc_potrf_static(B, m=None, info=None, stream=None):
+    """Handle-free dense Cholesky on a fixed per-GPU workspace (no device allocation).
+
+    B: column-major float64 view (lower triangle overwritten by R).  info: optional
+    int32 device tensor of one element; when given the call is asynchronous and
+    info receives 0 or 1 + the failing pivot."""
+    import torch
+    lib = load()
+    m = B.shape[0] if m is None else m
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    st = lib.sdpc_potrf_static(_ptr(B), Handle._ld(B, m), int(m), _ptr(info), C.c_void_p(stream.cuda_stream))
+    if st != SDPC_OK:
+        raise SdpcError(st, "sdpc_potrf_static: " + lib.sdpc_last_error(None).decode())
+    return B
 
 
 def sdpc_create(prob, stream=None, **params) -> Handle:
