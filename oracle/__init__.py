@@ -14,7 +14,8 @@ programs with positive matrix completion"):
   completion  max-determinant completion through the two-clique formula of
               the validity proof (Section 3.1), Algorithm 1 (Cholesky factor
               of the inverse of the completion), the textbook route
-              chol(inv(X^)) for comparison
+              chol(inv(X^)) for comparison, and the earlier sparse
+              factorisation X^ = L^T D L (Section 2.1)
   scm         the Schur complement matrix from its definition (eq. SCM) and
               the right-hand side of the Schur complement equation
   pdipm       a dense HKM primal-dual interior-point method (Section 2.2,
@@ -27,7 +28,7 @@ of the paper are listed in the module docstrings where they are used.
 """
 from .symbolic import Chordal, chordal_structure, sym_sparse, aggregate_pattern  # noqa: F401
 from .completion import (maxdet_complete, algorithm1, lhat_textbook,  # noqa: F401
-                         completion_by_vertex)
+                         completion_by_vertex, sparse_factors)
 from .scm import dense_scm, scm_rhs, scm_kron  # noqa: F401
 from .pdipm import (Params, dense_pdipm, mc_pdipm, mc_direction, dense_state_metrics,  # noqa: F401
                     step_length_dense, step_length_cliques)

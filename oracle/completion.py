@@ -21,6 +21,12 @@ algorithm1        Lhat of Algorithm 1 (Section 3.1): on the rows C_r, the
                   inverse of the clique block is formed and factorised
                   directly, so the two share no arithmetic.
 lhat_textbook     chol(inv(X^)), the definition Algorithm 1 must reproduce.
+sparse_factors    the earlier factorisation X^ = L^T D L (Section 2.1,
+                  eqs. sparse_fact, orig_L and orig_D): one elementary lower
+                  factor L_r per clique with X_UU^{-1} X_US in rows U_r,
+                  columns S_r; L = L_{l-1} ... L_1 multiplied out densely; D the
+                  block diagonal of the Schur complements X_SS - X_SU X_UU^{-1}
+                  X_US (X_SS itself for the last clique).
 """
 from __future__ import annotations
 
@@ -67,3 +73,22 @@ def algorithm1(ch: Chordal, Xbar: np.ndarray) -> np.ndarray:
 
 def lhat_textbook(Xhat: np.ndarray) -> np.ndarray:
     return np.linalg.cholesky(np.linalg.inv(Xhat))
+
+
+def sparse_factors(ch: Chordal, Xbar: np.ndarray):
+    """(L, D) with X^ = L^T D L, from their definitions (Section 2.1)."""
+    n = ch.n
+    L = np.eye(n)
+    D = np.zeros((n, n))
+    for r, C in enumerate(ch.cliques):
+        k = int(ch.nS[r])
+        S, U = C[:k], C[k:]
+        Lr = np.eye(n)
+        if len(U):
+            XUU = Xbar[np.ix_(U, U)]
+            Lr[np.ix_(U, S)] = np.linalg.solve(XUU, Xbar[np.ix_(U, S)])
+            D[np.ix_(S, S)] = Xbar[np.ix_(S, S)] - Xbar[np.ix_(S, U)] @ np.linalg.solve(XUU, Xbar[np.ix_(U, S)])
+        else:
+            D[np.ix_(S, S)] = Xbar[np.ix_(S, S)]
+        L = Lr @ L   # L = L_r ... L_1 after clique r
+    return L, D

@@ -143,3 +143,45 @@ def test_algorithm1_central_point():
     N = np.linalg.cholesky(Y)
     assert np.allclose(Lh, N / np.sqrt(mu), rtol=1e-10, atol=1e-12)
     assert np.allclose(maxdet_complete(ch, Xbar), mu * np.linalg.inv(Y), rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------ the earlier factorisation X^ = L^T D L
+# Pins of sparse_factors (Section 2.1, eqs. sparse_fact, orig_L, orig_D): its product must
+# be the max-determinant completion, which maxdet_complete reaches by a different formula
+# (the two-clique completion of the validity proof); L^{-1} keeps the sparsity of E (the
+# property the earlier solver's substitutions rely on); a three-vertex path worked by hand.
+@pytest.mark.parametrize("seed", range(5))
+def test_sparse_factors_reproduce_completion(seed):
+    from oracle.completion import sparse_factors
+    ch, Xbar, _ = _random_case(seed)
+    L, D = sparse_factors(ch, Xbar)
+    Xh = maxdet_complete(ch, Xbar)
+    assert np.abs(L.T @ D @ L - Xh).max() <= 1e-10 * np.abs(Xh).max()
+    assert np.array_equal(np.triu(L, 1), np.zeros_like(L)) and np.array_equal(np.diag(L), np.ones(ch.n))
+    Li = np.linalg.inv(L)
+    E = ch.E_mask()
+    assert np.abs(Li[~E]).max() <= 1e-12 * np.abs(Li).max()
+    # D is block diagonal over the supernodes S_r and positive definite
+    for r, C in enumerate(ch.cliques):
+        S = C[:int(ch.nS[r])]
+        others = np.setdiff1d(np.arange(ch.n), S)
+        assert np.abs(D[np.ix_(S, others)]).max(initial=0.0) == 0.0
+        assert np.linalg.eigvalsh(D[np.ix_(S, S)])[0] > 0
+    # and its inverse is Lhat Lhat^T of Algorithm 1
+    Lh = algorithm1(ch, Xbar)
+    assert np.abs(Li @ np.linalg.inv(D) @ Li.T - Lh @ Lh.T).max() <= 1e-10 * np.abs(Lh @ Lh.T).max()
+
+
+def test_sparse_factors_three_vertex_path_by_hand():
+    from oracle.completion import sparse_factors
+    # path 0 - 1 - 2: cliques {0, 1} (S = {0}, U = {1}) and {1, 2} (S = {1, 2})
+    ch = chordal_structure(3, np.array([0, 1, 1, 2, 2]), np.array([0, 0, 1, 1, 2]))
+    assert [list(C) for C in ch.cliques] == [[0, 1], [1, 2]] and list(ch.nS) == [1, 2]
+    x11, x21, x22, x32, x33 = 3.0, 1.0, 2.0, -0.5, 4.0
+    Xbar = np.array([[x11, x21, 0.0], [x21, x22, x32], [0.0, x32, x33]])
+    L, D = sparse_factors(ch, Xbar)
+    assert np.allclose(L, [[1, 0, 0], [x21 / x22, 1, 0], [0, 0, 1]], rtol=0, atol=1e-15)
+    assert np.allclose(D, [[x11 - x21 ** 2 / x22, 0, 0], [0, x22, x32], [0, x32, x33]], rtol=0, atol=1e-15)
+    Xh = L.T @ D @ L
+    assert abs(Xh[2, 0] - x32 * x21 / x22) <= 1e-15   # the classic max-det fill of a path
+    assert np.allclose(Xh[np.triu_indices(3)][[0, 1, 3, 4, 5]], [x11, x21, x22, x32, x33], atol=1e-15)
