@@ -164,6 +164,9 @@ def main():
     ap.add_argument("--workload", default="band4000",
                     help="band4000 (the metric's workload), latticeP (P x 10 lattice max-cut, e.g. lattice400) "
                          "or ktree256 (256 uneven k-tree max-cut SDPs, one plain solve each)")
+    ap.add_argument("--factorization", type=int, default=0, choices=(0, 1),
+                    help="0: X^ through Algorithm 1's Lhat (the method); 1: the earlier X^ = L^T D L "
+                         "(the factorisation ablation)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "potrf_traffic.json"),
                     help="HBM traffic per factorisation from rocprofv3 counters (json), if present")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -194,6 +197,8 @@ def main():
         batch_loop(args)
         return
     prob, cparams, desc = workload(args.workload)
+    if args.factorization:
+        cparams = dict(cparams, factorization=args.factorization)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = sdpc_create(prob, **cparams)
@@ -246,7 +251,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": prob.n, "m": m, "gap_tol": 1e-7,
-                   "block_width": int(h.params.block_width)},
+                   "block_width": int(h.params.block_width), "factorization": int(h.params.factorization)},
         "scm_s_per_iter": scm_per_iter,
         "iters": iters[0],
         "objective": (results[-1]["pobj"] + results[-1]["dobj"]) / 2,

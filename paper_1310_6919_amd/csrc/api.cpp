@@ -69,6 +69,7 @@ struct sdpc_handle {
     double *Xn = nullptr;   // the next X, formed before the iteration is known to have succeeded
     double *dX = nullptr, *dY = nullptr, *dz = nullptr;
     double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
+    double *Dblk = nullptr;   // factorization 1: D of X^ = L^T D L, w x w per storage block (Lhat holds L^{-1})
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
@@ -274,6 +275,13 @@ static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::v
     for (int b = 0; b < S.nb; ++b)
         h->d.max_panel = std::max<int64_t>(h->d.max_panel, (S.bl_rptr[b + 1] - S.bl_rptr[b]) *
                                                                 int64_t(S.bl_first[b + 1] - S.bl_first[b]));
+    if (h->prm.factorization == 1)
+        for (int r = 0; r < S.ncl; ++r)
+            if (S.col_block[S.cl_first[r]] != S.col_block[S.cl_first[r + 1] - 1])
+                return fail(h, SDPC_E_PATTERN, "factorization 1 needs every supernode inside one storage block (clique " +
+                                                   std::to_string(r) + " has " +
+                                                   std::to_string(S.cl_first[r + 1] - S.cl_first[r]) +
+                                                   " columns, wider than block_width)");
     if (solve_tile_width(h->d) == 0)
         return fail(h, SDPC_E_PATTERN, "substitution frontier too wide for LDS (" + std::to_string(h->d.nfwd) + "+" +
                                            std::to_string(h->d.nbwd) + " live rows)");
@@ -668,6 +676,10 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->hcol, size_t(m)));
     TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
+    if (h->prm.factorization == 1) {
+        TRY(dalloc(h, &h->Dblk, size_t(dinv_off.back())));
+        HIPCHK(h, hipMemsetAsync(h->Dblk, 0, size_t(dinv_off.back()) * sizeof(double), h->st));
+    }
     TRY(dalloc(h, &h->Xh, nn));
     TRY(dalloc(h, &h->Yi, nn));
     TRY(dalloc(h, &h->W, nn));
@@ -822,6 +834,17 @@ void read_scm_timing(sdpc_handle *h) {
     }
 }
 
+// The factor X^ is applied through, from Xbar: Lhat of Algorithm 1 (X^{-1} = Lhat
+// Lhat^T), or with factorization 1 the unit-lower L^{-1} and the block diagonal D of
+// X^ = L^T D L (eq. sparse_fact); then the inverses of the factor's diagonal blocks.
+void launch_xside(sdpc_handle *h, const double *Xbar, int *fail_clique, int *fail_dinv) {
+    if (h->prm.factorization == 1)
+        launch_ldl_cliques(h->d, Xbar, h->Lhat, h->Dblk, fail_clique, h->st);
+    else
+        launch_algorithm1(h->d, Xbar, h->Lhat, fail_clique, h->st);
+    launch_dinv(h->d, h->Lhat, h->DinvL, fail_dinv, h->st);
+}
+
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
 // Inside an iteration (in_step) the factor of Y may come from the dual step, the
 // X side may already have been formed at the end of the previous iteration, and
@@ -841,14 +864,11 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
     HIPCHK(h, hipEventRecord(h->evs[1], st));
-    if (!xready) {
-        launch_algorithm1(d, Xbar, h->Lhat, h->flags + kCand + 1, st);
-        launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
-    }
+    if (!xready) launch_xside(h, Xbar, h->flags + kCand + 1, h->flags + kCand);
     HIPCHK(h, hipEventRecord(h->evs[2], st));
     // Y^{-1} and X^ in one launch: the two walks are latency-bound and fill each
     // other's idle compute units
-    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st);
+    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st, nullptr, h->Dblk);
     h->xside_ready = false;
     HIPCHK(h, hipEventRecord(h->evs[3], st));
     if (d.hadamard)
@@ -967,8 +987,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
     // Lhat's diagonal inverses for the next iteration while the dual step runs
     const double gm = h->prm.gamma;
     launch_axpy_checked(d.nslot, h->X, h->dX, h->scal + 8, nullptr, gm, nullptr, 0, h->Xn, st);
-    launch_algorithm1(d, h->Xn, h->Lhat, h->flags + kCand + 3, st);
-    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand + 4, st);
+    launch_xside(h, h->Xn, h->flags + kCand + 3, h->flags + kCand + 4);
     HIPCHK(h, hipStreamWaitEvent(st, h->ev_dual, 0));   // join the dual step
     HIPCHK(h, hipEventRecord(ev[3], st));   // both step lengths are known
     // Step 4 for Y and z (alpha_d = bracket[0] on the device; the same fma as the
@@ -1198,9 +1217,8 @@ sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
     hipStream_t st = h->st;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand, 0, 8 * sizeof(int), st));
     h->xside_ready = false;
-    launch_algorithm1(d, h->X, h->Lhat, h->flags + kCand + 1, st);
-    launch_dinv(d, h->Lhat, h->DinvL, h->flags + kCand, st);
-    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st);
+    launch_xside(h, h->X, h->flags + kCand + 1, h->flags + kCand);
+    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st, h->Dblk);
     if (d_Xhat) launch_unpermute(d, h->Xh, d_Xhat, st);
     HIPCHK(h, hipGetLastError());
     int fl[2] = {0, 0};

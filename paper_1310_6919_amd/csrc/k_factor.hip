@@ -402,6 +402,90 @@ k_algorithm1(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_
         }
 }
 
+// The earlier factorisation X^ = L^T D L (eqs. sparse_fact, orig_L, orig_D of
+// Section 2.1), per clique C_r = S_r + U_r: the block in the order [U_r; S_r],
+// Z = [[X_UU, X_US], [X_SU, X_SS]], is eliminated over its first |U_r| columns
+// only.  That leaves the Schur complement X_SS - X_SU X_UU^{-1} X_US = D_r in the
+// trailing block, and the partially eliminated identity E = [[R^{-1}, 0],
+// [-X_SU X_UU^{-1}, I]] (X_UU = R R^T), whose lower-left block is the transpose
+// of the (U_r, S_r) block of L^{-1} = I - sum_r (L_r - I).  L^{-1}
+// (unit lower, on E, rows C_r x columns S_r) goes into the factor layout, D_r into
+// the w x w diagonal-block array of the storage block holding S_r (zero between
+// supernodes).  A second elimination of all |C_r| columns checks that D_r (hence
+// Xbar(C_r, C_r)) is positive definite.
+__global__ void __launch_bounds__(256)
+k_ldl_clique(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
+             const int *__restrict__ cl_map, const int *__restrict__ cl_first, const int *__restrict__ col_block,
+             const int *__restrict__ bl_first, const int64_t *__restrict__ bl_dinv,
+             const double *__restrict__ Xbar, double *__restrict__ Linv, double *__restrict__ Dblk,
+             int *__restrict__ fail) {
+    __shared__ TileLds<64, 64> sh;
+    const int r = blockIdx.x;
+    const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
+    const int ns = cl_first[r + 1] - cl_first[r];
+    const int nu = c - ns;
+    const int *map = cl_map + cl_map_ptr[r];
+    const int tid = threadIdx.x;
+    const int i0 = 4 * (tid / 16), j0 = 4 * (tid % 16);
+    auto pk = [c](int ii, int jj) { return jj * (2 * c - jj + 1) / 2 + (ii - jj); };
+    // Z index -> clique member: U first, then S
+    auto mem = [ns, nu](int z) { return z < nu ? ns + z : z - nu; };
+    auto xval = [&](int za, int zb) {   // Xbar(member(za), member(zb))
+        int ii = mem(za), jj = mem(zb);
+        if (ii < jj) { const int t = ii; ii = jj; jj = t; }
+        return Xbar[map[pk(ii, jj)]];
+    };
+    double a[4][4], e[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            a[u][v] = (i < c && k <= i) ? xval(i, k) : (i == k ? 1.0 : 0.0);
+            e[u][v] = (i == k) ? 1.0 : 0.0;
+        }
+    int bad = 0;
+    if (!chol_tile<4, 4, 16, true>(a, e, nu, sh, &bad)) {
+        if (tid == 0) atomicCAS(fail, 0, r + 1);
+        return;
+    }
+    // D_r: the trailing block (lower triangle valid), stored symmetric
+    const int F = cl_first[r], b = col_block[F], Fb = bl_first[b], w = bl_first[b + 1] - Fb;
+    double *Db = Dblk + bl_dinv[b];
+    const int s0 = F - Fb;   // first column of S_r inside the storage block
+    double dkeep[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            dkeep[u][v] = a[u][v];
+            if (i < c && k <= i && k >= nu) {
+                const int si = i - nu, sk = k - nu;
+                Db[(s0 + si) + w * (s0 + sk)] = a[u][v];
+                Db[(s0 + sk) + w * (s0 + si)] = a[u][v];
+            }
+            // (U_r, S_r) block of L^{-1}: Linv(member ns + k, member i - nu) = E(i, k)
+            if (i < c && i >= nu && k < nu) Linv[map[pk(ns + k, i - nu)]] = e[u][v];
+        }
+    for (int t = tid; t < ns * (ns + 1) / 2; t += blockDim.x) {   // S_r x S_r block: the identity
+        int jj = 0, rem = t;
+        while (rem >= ns - jj) { rem -= ns - jj; ++jj; }
+        const int ii = jj + rem;
+        Linv[map[pk(ii, jj)]] = (ii == jj) ? 1.0 : 0.0;
+    }
+    // D_r positive definite: eliminate it on its own (identity in the U rows)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + u, k = j0 + v;
+            a[u][v] = (i < c && k <= i && k >= nu) ? dkeep[u][v] : (i == k ? 1.0 : 0.0);
+        }
+    if (!chol_tile<4, 4, 16, false>(a, e, c, sh, &bad))
+        if (tid == 0) atomicCAS(fail, 0, r + 1);
+}
+
 __global__ void __launch_bounds__(256)
 k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
            const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
@@ -630,6 +714,12 @@ void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, h
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail, hipStream_t st) {
     hipLaunchKernelGGL(k_algorithm1, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map,
                        d.cl_first, Xbar, Lhat, fail);
+}
+
+void launch_ldl_cliques(const DevStruct &d, const double *Xbar, double *Linv, double *Dblk, int *fail,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_ldl_clique, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, d.cl_first,
+                       d.col_block, d.bl_first, d.bl_dinv, Xbar, Linv, Dblk, fail);
 }
 
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX, double *alpha_cl,

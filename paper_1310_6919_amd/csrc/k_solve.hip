@@ -21,6 +21,12 @@
 // block is processed, so a walk pays one memory latency at its start instead of
 // one per block.  Finally the lower triangle is mirrored to make the output
 // symmetric.
+//
+// The earlier factorisation X^ = L^T D L (Section 2.1, eq. sparse_fact) runs
+// through the same walks with the sparse unit-lower L^{-1} as the factor: the
+// forward walk gives L e_k, the block-diagonal D (w x w per storage block,
+// zero between supernodes) multiplies each block's part of it before it is
+// stored, and the backward walk applies L^T.
 #include "kernels.h"
 
 namespace sdpc {
@@ -101,12 +107,14 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             const int *__restrict__ bl_fslot, const int *__restrict__ bl_bslot,
             const int64_t *__restrict__ bl_dinv, const int *__restrict__ col_block, int nfwd, int nbwd,
             const double *__restrict__ L0, const double *__restrict__ Dinv0, double *__restrict__ out0,
-            const double *__restrict__ L1, const double *__restrict__ Dinv1, double *__restrict__ out1) {
+            const double *__restrict__ L1, const double *__restrict__ Dinv1, double *__restrict__ out1,
+            const double *__restrict__ Dm0, const double *__restrict__ Dm1) {
     // blockIdx.y picks one of two independent factors (they share the block layout),
     // so both inverses are formed by one launch and its workgroups interleave
     const double *L = blockIdx.y ? L1 : L0;
     const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
     double *out = blockIdx.y ? out1 : out0;
+    const double *Dm = blockIdx.y ? Dm1 : Dm0;   // block diagonal between the walks, or null
     extern __shared__ double sm[];
     double *const Pbuf0 = sm, *const Pbuf1 = sm + pcap;      // pcap >= every h * w
     double *const Dbuf0 = sm + 2 * pcap, *const Dbuf1 = sm + 2 * pcap + maxw * maxw;
@@ -190,16 +198,38 @@ k_inv_solve(int n, int nb, int maxw, int maxh, int pcap, const int *__restrict__
             }
             xo[i0 * T + c0] = s00;
             xo[i0 * T + c0 + 1] = s01;
-            if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i0] = s00;
-            if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i0] = s01;
+            if (!Dm && k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i0] = s00;
+            if (!Dm && k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i0] = s01;
             if (r1) {
                 xo[i1 * T + c0] = s10;
                 xo[i1 * T + c0 + 1] = s11;
-                if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i1] = s10;
-                if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i1] = s11;
+                if (!Dm && k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i1] = s10;
+                if (!Dm && k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i1] = s11;
             }
         }
         __syncthreads();
+        if (Dm) {   // the forward result stored for the backward walk is D_b xo
+            const double *Db = Dm + bl_dinv[b];
+            for (int blk = tid; blk < ((w + 1) / 2) * TP; blk += kThreads) {
+                const int i0 = 2 * (blk / TP), c0 = 2 * (blk % TP), i1 = i0 + 1;
+                const bool r1 = i1 < w;
+                double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+                for (int j = 0; j < w; ++j) {
+                    const double d0 = Db[i0 + w * j], d1 = r1 ? Db[i1 + w * j] : 0.0;
+                    const double v0 = xo[j * T + c0], v1 = xo[j * T + c0 + 1];
+                    s00 = fma(d0, v0, s00);
+                    s01 = fma(d0, v1, s01);
+                    s10 = fma(d1, v0, s10);
+                    s11 = fma(d1, v1, s11);
+                }
+                if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i0] = s00;
+                if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i0] = s01;
+                if (r1) {
+                    if (k0 + c0 < n) out[int64_t(n) * (k0 + c0) + F + i1] = s10;
+                    if (k0 + c0 + 1 < n) out[int64_t(n) * (k0 + c0 + 1) + F + i1] = s11;
+                }
+            }
+        }
         // pending updates of the rows below the block: acc(U) -= P21 xo
         for (int blk = tid; blk < ((hw + 1) / 2) * TP; blk += kThreads) {
             const int a0 = 2 * (blk / TP), c0 = 2 * (blk % TP), a1 = a0 + 1;
@@ -352,6 +382,23 @@ __device__ inline d4 mma32(FA fa, FB fb) {
     return a0 + a1;
 }
 
+// mma32 with this lane's B operands already in registers (zb[ks] for
+// k = 4 ks + l / 16).
+template <typename FA>
+__device__ inline d4 mma32_breg(FA fa, const double (&zb)[8]) {
+    const int lq = (threadIdx.x & 63) >> 4;
+    double xa[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) xa[ks] = fa(4 * ks + lq);
+    d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+    for (int ks = 0; ks < 8; ks += 2) {
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks], zb[ks], a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks + 1], zb[ks + 1], a1, 0, 0, 0);
+    }
+    return a0 + a1;
+}
+
 // The same walks with T = 16 right-hand sides, blocks of width <= 32, and every
 // dense product of a block step on the FP64 MFMA (16 x 16 x 4; lane l supplies
 // A(l % 16, l / 16) and B(l / 16, l % 16), element r of the result is
@@ -365,11 +412,13 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
                 const int *__restrict__ bl_bslot, const int64_t *__restrict__ bl_dinv,
                 const int *__restrict__ col_block, int nfwd, int nbwd, const double *__restrict__ L0,
                 const double *__restrict__ Dinv0, double *__restrict__ out0, const double *__restrict__ L1,
-                const double *__restrict__ Dinv1, double *__restrict__ out1) {
+                const double *__restrict__ Dinv1, double *__restrict__ out1, const double *__restrict__ Dm0,
+                const double *__restrict__ Dm1) {
     constexpr int T = kRhs;
     const double *L = blockIdx.y ? L1 : L0;
     const double *Dinv = blockIdx.y ? Dinv1 : Dinv0;
     double *out = blockIdx.y ? out1 : out0;
+    const double *Dm = blockIdx.y ? Dm1 : Dm0;   // block diagonal between the walks, or null
     extern __shared__ double sm[];
     double *const Pbuf0 = sm, *const Pbuf1 = sm + pcap;
     double *const Dbuf0 = sm + 2 * pcap, *const Dbuf1 = sm + 2 * pcap + maxw * maxw;
@@ -420,6 +469,15 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         return d;
     };
     double rp[kPanelPer], rd[kDinvPer];
+    // with D: this lane's operands of D_b (waves 0 and 1), D(16 wv + l % 16, 4 ks + l / 16),
+    // for the current block and, prefetched with its panel, the next one
+    double dmr[8], dmn[8];
+    auto fetch_dm = [&](int bb, double (&z)[8]) {
+        const SolveDesc &e = desc[bb];
+        const int i = min(16 * wv + li, e.w - 1);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) z[ks] = Dm[e.doff + i + e.w * min(4 * ks + lq, e.w - 1)];
+    };
     // ------------------------------------------------------------ forward
     int cur = 0;
     int b = active(b0) ? b0 : next_active(b0);
@@ -428,6 +486,7 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         fetch_block(d, rp, rd);
         put_block(d, rp, rd, Pbuf0, Dbuf0);
         for (int i = tid; i < d.h; i += kThreads) slots0[i] = bl_fslot[d.r0 + i];
+        if (Dm && wv < 2) fetch_dm(b, dmr);
     }
     __syncthreads();
     while (b < nb) {
@@ -439,6 +498,7 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
             dn = bdesc(bn);
             fetch_block_nb(dn, rp, rd);   // in flight during this block's work
             fsn = bl_fslot[dn.r0 + min(tid, dn.h - 1)];
+            if (Dm && wv < 2) fetch_dm(bn, dmn);
         }
         const double *Pn = ((cur) ? Pbuf1 : Pbuf0), *Dn = ((cur) ? Dbuf1 : Dbuf0);
         const int *fsl = ((cur) ? slots1 : slots0);
@@ -476,11 +536,32 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
                 for (int r = 0; r < 4; ++r) {
                     const int c = 4 * r + lq;
                     xo[i * T + c] = acc[r];
-                    if (k0 + c < n) out[int64_t(n) * (k0 + c) + F + i] = acc[r];
+                    if (!Dm && k0 + c < n) out[int64_t(n) * (k0 + c) + F + i] = acc[r];
                 }
             }
         }
         __syncthreads();
+        // with D: the forward result stored for the backward walk is D_b xo, as
+        // (D_b xo)^T = xo^T D_b^T: element (c, i)
+        if (Dm && wv < (w + 15) / 16) {
+            const int i = 16 * wv + li;
+            double zb[8];
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) zb[ks] = (4 * ks + lq < w && i < w) ? dmr[ks] : 0.0;
+            const d4 acc = mma32_breg(
+                [&](int k) {
+                    const double x = xo[min(k, w1) * T + li];
+                    return (k < w) ? x : 0.0;
+                },
+                zb);
+            if (i < w) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = 4 * r + lq;
+                    if (k0 + c < n) out[int64_t(n) * (k0 + c) + F + i] = acc[r];
+                }
+            }
+        }
         // pending updates of the rows below the block: acc(U) -= P21 xo, element (a, c)
         for (int rt = wv; rt < (hw + 15) / 16; rt += 4) {
             const int a = 16 * rt + li, ac = min(a, hw1);
@@ -502,6 +583,10 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
         if (bn < nb) {
             put_block(dn, rp, rd, ((cur ^ 1) ? Pbuf1 : Pbuf0), ((cur ^ 1) ? Dbuf1 : Dbuf0));
             if (tid < dn.h) ((cur ^ 1) ? slots1 : slots0)[tid] = fsn;
+            if (Dm) {
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) dmr[ks] = dmn[ks];
+            }
         }
         __syncthreads();
         cur ^= 1;
@@ -646,14 +731,15 @@ int solve_tile_width(const DevStruct &d) {
 }
 
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
-                              const double *L1, const double *Dinv1, double *out1, hipStream_t st) {
+                              const double *L1, const double *Dinv1, double *out1, hipStream_t st,
+                              const double *Dm0, const double *Dm1) {
     const int nf = L1 ? 2 : 1;
     const int nt = (d.n + 31) / 32;
     if (!d.solve_generic && solve_mma_ok(d)) {
         hipLaunchKernelGGL(k_inv_solve_mma, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), solve_lds_mma(d), st,
                            d.n, d.nb, d.max_w, d.max_h, solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off,
                            d.bl_subfirst, d.bl_fslot, d.bl_bslot, d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0,
-                           out0, L1, Dinv1, out1);
+                           out0, L1, Dinv1, out1, Dm0, Dm1);
         hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
         return;
     }
@@ -663,7 +749,7 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
 #define SDPC_SOLVE(TT)                                                                                     \
     hipLaunchKernelGGL(k_inv_solve<TT>, dim3(grid, nf), dim3(kThreads), lds, st, d.n, d.nb, d.max_w, d.max_h, \
                        solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_bslot,   \
-                       d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0, out0, L1, Dinv1, out1)
+                       d.bl_dinv, d.col_block, d.nfwd, d.nbwd, L0, Dinv0, out0, L1, Dinv1, out1, Dm0, Dm1)
     switch (T) {
         case 16: SDPC_SOLVE(16); break;
         case 8: SDPC_SOLVE(8); break;

@@ -164,15 +164,26 @@ void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, h
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,
                        hipStream_t st);
+// the earlier factorisation X^ = L^T D L (eqs. sparse_fact, orig_L, orig_D): per
+// clique the (C_r, S_r) columns of the unit-lower L^{-1} (factor layout) and D_r
+// (w x w blocks at bl_dinv; the blocks must be zeroed once, entries between
+// supernodes stay zero); needs every supernode inside one storage block; fail =
+// 1 + clique on a non-PD block
+void launch_ldl_cliques(const DevStruct &d, const double *Xbar, double *Linv, double *Dblk, int *fail,
+                        hipStream_t st);
 // eq. primal_length2: per-clique maximal step, then the minimum into *out
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX,
                           double *alpha_cl, double *out, hipStream_t st);
 
 // ---- sparse substitutions (k_solve.hip): out = (L L^T)^{-1}, n x n, full symmetric
 int solve_tile_width(const DevStruct &d);
-// out_f = L_f^{-T} L_f^{-1} (dense n x n) for one or two factors (L1 == nullptr: one)
+// out_f = L_f^{-T} L_f^{-1} (dense n x n) for one or two factors (L1 == nullptr: one);
+// with Dm_f != nullptr (w x w blocks at bl_dinv, block diagonal over the supernodes)
+// out_f = L_f^{-T} Dm_f L_f^{-1} instead: with L_f^{-1} of eq. sparse_fact as the
+// factor this is X^ = L^T D L
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
-                              const double *L1, const double *Dinv1, double *out1, hipStream_t st);
+                              const double *L1, const double *Dinv1, double *out1, hipStream_t st,
+                              const double *Dm0 = nullptr, const double *Dm1 = nullptr);
 
 // ---- Schur complement (k_scm.hip)
 void launch_scm_hadamard(const DevStruct &d, const double *Xh, const double *Yi, double *B,
