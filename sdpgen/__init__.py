@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "Problem", "from_matrices", "maxcut", "cycle_graph", "complete_graph",
     "grid_graph", "lattice_graph", "random_graph", "chordal_band_graph",
-    "maxcut_cycle_chords", "maxcut_band", "normmin", "random_ktree_graph",
+    "maxcut_cycle_chords", "maxcut_band", "maxcut_adjoint_case", "normmin", "random_ktree_graph",
     "maxcut_ktree_batch", "random_pd_dense", "random_pd_on_pattern",
 ]
 
@@ -203,6 +203,26 @@ def maxcut_band(n: int = 4000, bw: int = 20, p: float = 0.5, seed: int = 0,
     w = rng.uniform(wlo, whi, len(edges))
     return maxcut(n, edges, w, name=f"maxcut_band_n{n}_bw{bw}_s{seed}",
                   meta={"bandwidth": bw})
+
+
+def maxcut_adjoint_case(n: int = 2000, bw: int = 16, seed: int = 0, nedges: int = 20):
+    """Differentiation workload: the max-cut SDP over the full band of width bw
+    (every pair 1 <= j - i <= bw, weights U[0.5, 1.5]), a loss matrix G_L that is
+    symmetric with N(0,1) entries on |i - j| <= bw (diagonal included; returned as
+    lower triplets), and nedges edge indices sampled uniformly without
+    replacement.  Returns (problem, (rows, cols, vals) of G_L, edge indices)."""
+    prob = maxcut_band(n, bw, 1.0, seed, 0.5, 1.5)
+    rng = np.random.default_rng(seed + 1)
+    gr, gc = [], []
+    for j in range(n):
+        hi = min(n, j + bw + 1)
+        gr.append(np.arange(j, hi))
+        gc.append(np.full(hi - j, j))
+    gr = np.concatenate(gr).astype(np.int32)
+    gc = np.concatenate(gc).astype(np.int32)
+    gv = rng.standard_normal(len(gr))
+    sel = rng.choice(len(prob.meta["weights"]), size=min(nedges, len(prob.meta["weights"])), replace=False)
+    return prob, (gr, gc, gv), np.sort(sel)
 
 
 def maxcut_lattice(p: int = 400, q: int = 10, seed: int = 0, wlo: float = 0.0, whi: float = 1.0) -> Problem:
