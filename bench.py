@@ -9,9 +9,21 @@ upload of the problem) is created before the timed region, so the inputs are
 resident in HBM when it starts.  Prints one JSON line:
 
   value            solves per second (whole job, one GPU)
-  scm_s_per_iter   device time per iteration of the Schur complement phase:
-                   Y factor, Algorithm 1, substitutions, SCM assembly and the
-                   right-hand side, plus the SCM Cholesky and SCE solve
+  scm_s_per_iter   device time of one Schur complement evaluation on its own
+                   (sdpc_scm at the final iterate, median of 5): Y = N N^T,
+                   the X factor (Algorithm 1), the substitutions forming X^ and
+                   Y^{-1}, the SCM assembly and the SCM Cholesky
+  scm_s_per_iter_in_solve
+                   the same phases as they run inside a solve, per iteration:
+                   there the factor of Y comes from the dual step and the X
+                   factor is formed in the previous iteration's shadow, so only
+                   the substitutions, the assembly with the right-hand side and
+                   the Cholesky with the SCE solve are on the iteration's path
+  phase_roofline   per phase of the standalone evaluation: its algorithmic bytes
+                   and flops, achieved GB/s and GFLOP/s, and the fraction of the
+                   roofline max(bytes / 8 TB/s, flops / 78.6 TFLOP/s) / time
+  measured_peaks   a 1 GiB device copy and an FP64 GEMM (n = 8192, the vendor
+                   library) timed on this GPU, beside the datasheet peaks
   roofline         the SCM Cholesky (the largest dense kernel of an iteration):
                    m^3/3 FP64 flops per factorisation over its average device
                    time, measured with events on the library's stream during
@@ -50,6 +62,20 @@ def log(msg):
 
 
 BAND = "maxcut-band n=m=4000 bandwidth 20 p=0.5 w~U[0,1] seed 0"
+NORMMIN = ("norm-min [[t I, F(y)], [F(y)^T, t I]], F_i 2000 x 10 ~ N(0,1)/sqrt(2000), 63 y's plus t "
+           "(n=2010, m=64), seed 0")
+CYCLE = "maxcut cycle + chords at cyclic distance <=4 (p=0.5), n=m=64, w~U[0,1], seed 0"
+GOLDEN = {"band4000": "oracle_cfg2.json", "normmin": "oracle_cfg3.json", "cfg1": "oracle_cfg1_s0.json"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def workload(name="band4000"):
@@ -60,6 +86,10 @@ def workload(name="band4000"):
     import sdpgen
     if name == "band4000":
         return sdpgen.maxcut_band(4000, 20, 0.5, 0), {}, BAND
+    if name == "normmin":
+        return sdpgen.normmin(2000, 10, 63, 0), {}, NORMMIN
+    if name == "cfg1":
+        return sdpgen.maxcut_cycle_chords(64, 0), {}, CYCLE
     if name.startswith("lattice"):
         p = int(name[len("lattice"):])
         prob = sdpgen.maxcut_lattice(p, 10, 0)
@@ -69,16 +99,50 @@ def workload(name="band4000"):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(prob, iters):
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        return os.cpu_count()
+
+
+def cpu_full_solves(prob, runs=6):
+    """Whole oracle solves to gap 1e-7 (small instances): median of runs - 1 after a
+    discarded first run, on all BLAS threads and on one."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    out = {}
+    for label, limit in (("all_threads", None), ("one_thread", 1)):
+        times = []
+        with threadpool_limits(limits=limit):
+            threads = blas_threads()
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                res = oracle.dense_pdipm(prob, oracle.Params())
+                times.append(time.perf_counter() - t0)
+        med = statistics.median(times[1:])
+        out[label] = {"value": 1.0 / med, "s_per_solve": med, "cores": int(threads), "iters": int(res["iters"])}
+    best = out["all_threads"]
+    return {
+        "value": best["value"],
+        "unit": "solves/s",
+        "cores": best["cores"],
+        "kind": "oracle",
+        "sample": (f"whole dense-oracle solves to gap 1e-7 ({best['iters']} iterations), median of {runs - 1} "
+                   f"after a discarded first run; single-threaded: {out['one_thread']['value']:.2f} solves/s"),
+        "one_thread": out["one_thread"],
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def cpu_baseline(prob, iters, golden="oracle_cfg2.json"):
     """Time the oracle's first `iters` iterations on the same instance."""
     import numpy as np  # noqa: F401
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        threads = os.cpu_count()
-    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_cfg2.json")))
+    threads = blas_threads()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", golden)))
     n_it = gold.get("iters_to_1e-7") or gold["iters"]
     t0 = time.perf_counter()
     res = oracle.dense_pdipm(prob, oracle.Params(), max_iter=iters)
@@ -96,8 +160,128 @@ def cpu_baseline(prob, iters):
                    f"the oracle takes to reach gap 1e-7"),
         "s_per_iter": per_iter,
         "scm_s_per_iter": statistics.mean(t_scm),
+        "cpu_model": cpu_model(),
         "host_cpus": os.cpu_count(),
     }
+
+
+def measured_peaks():
+    """A 1 GiB device-to-device copy (read + write) and an FP64 GEMM of order 8192
+    through the vendor library, timed with events on torch's stream."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    a = torch.randn(8192, 8192, dtype=torch.float64, device="cuda")
+    b = torch.randn(8192, 8192, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):
+        dst.copy_(src)
+        c = a @ b
+    ev[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(3):
+        c = a @ b
+    ev[3].record()
+    torch.cuda.synchronize()
+    copy_s = ev[0].elapsed_time(ev[1]) / 5 / 1e3
+    gemm_s = ev[2].elapsed_time(ev[3]) / 3 / 1e3
+    del src, dst, a, b, c
+    torch.cuda.empty_cache()
+    return {"copy_GBs": 2 * (1 << 30) / copy_s / 1e9, "dgemm_TFLOPs": 2 * 8192.0 ** 3 / gemm_s / 1e12,
+            "datasheet_hbm_GBs": HBM_PEAK_GBS, "datasheet_fp64_mfma_TFLOPs": FP64_MFMA_PEAK_TFLOPS}
+
+
+def solve_flops(h):
+    """Flops of the substitutions forming one dense inverse L^{-T} L^{-1} column by
+    column with the sparse factor (pattern of E): for column k the forward solve runs
+    over the elimination-tree ancestors of k, the backward solve (rows >= k only) over
+    every column >= k; 2 flops per stored entry of each column visited."""
+    import numpy as np
+    iE, jE, perm = h.sdpc_get_pattern()
+    pos = np.empty(len(perm), dtype=np.int64)
+    pos[perm] = np.arange(len(perm))
+    ok = iE >= 0
+    pi, pj = pos[iE[ok]], pos[jE[ok]]
+    n = len(perm)
+    cc = np.bincount(pj, minlength=n).astype(np.float64)
+    off = pi > pj
+    parent = np.full(n, -1, dtype=np.int64)
+    first_below = np.full(n, n, dtype=np.int64)
+    np.minimum.at(first_below, pj[off], pi[off])
+    parent[first_below < n] = first_below[first_below < n]
+    anc = cc.copy()
+    for k in range(n - 1, -1, -1):   # parents have larger positions
+        if parent[k] >= 0:
+            anc[k] += anc[parent[k]]
+    suffix = np.cumsum(cc[::-1])[::-1]
+    return float(2.0 * (anc.sum() + suffix.sum()))
+
+
+def assembly_work(prob):
+    """(Hadamard form?, flops of the general assembly): per constraint q the product
+    X^ A_q over the nonzero columns of A_q (2 n nnz(A_q)) and the support-restricted
+    product with Y^{-1} (2 |support| |K_q|)."""
+    import numpy as np
+    had = True
+    sup = set()
+    per_q = []
+    for k in range(1, prob.m + 1):
+        r, c, v = prob.triplets(k)
+        nz = v != 0
+        r, c = r[nz], c[nz]
+        if not (len(r) and np.all(r == c) and np.all(r == r[0])):
+            had = False
+        cols = set(c.tolist()) | set(r.tolist())
+        nnz_full = len(r) + int(np.sum(r != c))
+        per_q.append((nnz_full, len(cols)))
+        sup.update(zip(r.tolist(), c.tolist()))
+        sup.update(zip(c.tolist(), r.tolist()))
+    S = len(sup)
+    return had, float(sum(2.0 * prob.n * nz + 2.0 * S * kq for nz, kq in per_q))
+
+
+def standalone_scm(h, prob, reps=5):
+    """One Schur complement evaluation on its own at the handle's current iterate,
+    phase by phase (median of reps), with the algorithmic work of each phase."""
+    import torch
+    X, Y, _ = h.sdpc_get_solution()
+    B = torch.empty(prob.m, prob.m, dtype=torch.float64, device="cuda").T
+    rows = []
+    for _ in range(reps):
+        h.sdpc_scm(X, Y, B, factor=True)
+        rows.append(h.sdpc_get_scm_timing())
+    med = [statistics.median(r[i] for r in rows) for i in range(5)]
+    n, m = prob.n, prob.m
+    had, fl_asm = assembly_work(prob)
+    # algorithmic work: the substitutions write X^ and Y^{-1} (n^2 doubles each); the
+    # max-cut assembly reads both lower triangles and writes B's, the general one does
+    # the dense x sparse and support-restricted products; the Cholesky does m^3 / 3
+    # flops on B's lower triangle, read and written once
+    phases = {
+        "y_factor": {"ms": med[0], "bound": "latency"},
+        "x_factor": {"ms": med[1], "bound": "latency"},
+        "solves": {"ms": med[2], "bytes": 2 * 8.0 * n * n, "flops": 2 * solve_flops(h)},
+        "assembly": {"ms": med[3], "bytes": (3 * 8.0 * m * (m + 1) / 2) if had else None,
+                     "flops": None if had else fl_asm},
+        "cholesky": {"ms": med[4], "bytes": 2 * 8.0 * m * (m + 1) / 2, "flops": m ** 3 / 3.0},
+    }
+    for ph in phases.values():
+        t = ph["ms"] * 1e-3
+        if t <= 0:
+            continue
+        bt = ph.get("bytes")
+        ft = ph.get("flops")
+        if bt:
+            ph["achieved_GBs"] = bt / t / 1e9
+        if ft:
+            ph["achieved_GFLOPs"] = ft / t / 1e9
+        if bt or ft:
+            ideal = max((bt or 0) / (HBM_PEAK_GBS * 1e9), (ft or 0) / (FP64_MFMA_PEAK_TFLOPS * 1e12))
+            ph["frac"] = ideal / t
+    return sum(med) * 1e-3, phases
 
 
 def batch_loop(args):
@@ -161,8 +345,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy / FP64 GEMM peak measurement")
     ap.add_argument("--workload", default="band4000",
-                    help="band4000 (the metric's workload), latticeP (P x 10 lattice max-cut, e.g. lattice400) "
+                    help="band4000 (the metric's workload), normmin (norm minimisation, n = 2010, m = 64), "
+                         "cfg1 (max-cut, n = m = 64), latticeP (P x 10 lattice max-cut, e.g. lattice400) "
                          "or ktree256 (256 uneven k-tree max-cut SDPs, one plain solve each)")
     ap.add_argument("--factorization", type=int, default=0, choices=(0, 1),
                     help="0: X^ through Algorithm 1's Lhat (the method); 1: the earlier X^ = L^T D L "
@@ -222,7 +408,8 @@ def main():
         if r["status"] != 0:
             raise SystemExit(f"solve failed: {r}")
     iters = [r["iters"] for r in results]
-    scm_per_iter = statistics.median([(r["t_scm_ms"] + r["t_chol_ms"]) / r["iters"] / 1e3 for r in results])
+    scm_in_solve = statistics.median([(r["t_scm_ms"] + r["t_chol_ms"]) / r["iters"] / 1e3 for r in results])
+    scm_alone, phases = standalone_scm(h, prob)
     potrf_ms = sum(r["t_potrf_ms"] for r in results) / max(1, sum(r["n_potrf"] for r in results))
     m = prob.m
     launches = (m + 63) // 64
@@ -252,7 +439,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": prob.n, "m": m, "gap_tol": 1e-7,
                    "block_width": int(h.params.block_width), "factorization": int(h.params.factorization)},
-        "scm_s_per_iter": scm_per_iter,
+        "scm_s_per_iter": scm_alone,
+        "scm_s_per_iter_in_solve": scm_in_solve,
+        "phase_roofline": phases,
         "iters": iters[0],
         "objective": (results[-1]["pobj"] + results[-1]["dobj"]) / 2,
         "create_ms": create_ms,
@@ -284,9 +473,14 @@ def main():
         total = float(prob.meta["weights"].sum())
         out["optimum_closed_form"] = -total
         out["objective_rel_err"] = abs(out["objective"] + total) / total
-    if not args.no_cpu_baseline and args.workload == "band4000":
+    if not args.no_peaks:
+        out["measured_peaks"] = measured_peaks()
+    if not args.no_cpu_baseline and args.workload == "cfg1":
+        log("cpu baseline: whole oracle solves ...")
+        out["cpu_baseline"] = cpu_full_solves(prob)
+    elif not args.no_cpu_baseline and args.workload in GOLDEN:
         log(f"cpu baseline: {args.cpu_iters} oracle iterations on the same instance ...")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters, GOLDEN[args.workload])
     print(json.dumps(out), flush=True)
 
 

@@ -99,7 +99,11 @@ typedef struct {
                                   factorisation X^ = L^T D L (eq. sparse_fact, Section 2.1),
                                   substituting with the sparse L^{-1} around the block
                                   diagonal D                                       (0)      */
-    int32_t reserved_;         /* 0                                                        */
+    int32_t merge_siblings;    /* storage blocks: 1 also merges consecutive sibling
+                                  subtrees of the elimination tree whose rows below the
+                                  block do not grow (explicit zeros only: E and every
+                                  result are unchanged, the block walks get shorter);
+                                  0 merges chains only                             (1)      */
     const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
                                   i-th (host, read at create)                              */
 } sdpc_params;
@@ -268,6 +272,36 @@ sdpc_status sdpc_get_direction(const sdpc_handle *h, double *d_dz, double *d_dX_
  * [Y factor, Algorithm 1, solves, SCM assembly, SCM Cholesky].  Host array
  * of 5.  Synchronises. */
 sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5);
+
+/* Centring: Newton steps of Step 2 of Section 2.2 from the handle's current
+ * iterate with the centring target beta mu replaced by the fixed mu (> 0), so
+ * that the iterate converges to the point of the central path with
+ * X^ Y = mu I, A(X) = b and sum_k z_k A_k + Y = A_0 (step lengths as in Steps
+ * 3-4).  The stopping test of Step 1 is not applied.  Stops after max_steps
+ * steps or once a step moves z by at most tol relative to max(1, max|z|).
+ * steps (host, optional) receives the steps taken, last_rel_step (host,
+ * optional) that relative move.  A failed step leaves the iterate as it was
+ * and returns its status.  Synchronises. */
+sdpc_status sdpc_center(sdpc_handle *h, double mu, int32_t max_steps, double tol, int32_t *steps,
+                        double *last_rel_step);
+
+/* Derivatives of a loss L(X, z) at the handle's current iterate, taken to be a
+ * point of the central path (sdpc_center): the central point is a smooth
+ * function of (b, A_0) for fixed mu, and differentiating its three equations
+ * leads to the Schur complement matrix B of eq. SCM (not part of the paper's
+ * method; the same matrix and substitutions are reused).  Inputs: d_GL_E
+ * (device E-vector), the symmetric gradient of L with respect to X, which must
+ * vanish off the aggregate sparsity pattern (entries there are ignored: the
+ * completion X^ equals Xbar only on E); d_dLdz (device, length m, may be NULL
+ * for 0), the gradient with respect to z.  Outputs (device):
+ *   d_gb   (length m)  dL/db = lambda = B^{-1} (h + dL/dz), h_p = A_p . (X^ G_L Y^{-1})
+ *   d_gC_E (E-vector)  dL/dA_0 = sym(X^ (sum_k lambda_k A_k - G_L) Y^{-1}) on E, in the
+ *                      Frobenius product: a change of A_0 by a symmetric dA_0
+ *                      supported on E changes L by sum_ij (dL/dA_0)_ij (dA_0)_ij.
+ * Overwrites the buffers sdpc_get_dense and sdpc_get_factors read.  Returns
+ * SDPC_E_NOT_PD if a factorisation fails.  Synchronises. */
+sdpc_status sdpc_adjoint(sdpc_handle *h, const double *d_GL_E, const double *d_dLdz, double *d_gb,
+                         double *d_gC_E);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the dense

@@ -69,7 +69,7 @@ def adjoint(prob, X, Y, z, GL, dLdz):
     Yinv = _inv_spd(Y)
     B = dense_scm(A, X, Yinv)
     T = X @ GL @ Yinv
-    h = np.array([np.sum(A[k].toarray() * T) for k in range(1, prob.m + 1)])
+    h = np.array([float(A[k].multiply(T).sum()) for k in range(1, prob.m + 1)])
     lam = sla.cho_solve(sla.cho_factor(B, lower=True), h + dLdz)
     M = ops.combine(lam, n) - GL
     Gam = X @ M @ Yinv

@@ -73,6 +73,7 @@ struct sdpc_handle {
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
     double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
+    double *ccwork = nullptr; // blocks of the column-compressed general SCM (cc_work_doubles)
     double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
     double *mwork = nullptr;  // partial results of the metrics
     double *ydw = nullptr, *ydw_dual = nullptr;   // row-major (Y, dY) tiles of the Y factor / dual step
@@ -175,7 +176,7 @@ sdpc_params sdpc_default_params(void) {
     p.pool_lds_bytes = 32 * 1024;
     p.solve_kernel = 0;
     p.factorization = 0;
-    p.reserved_ = 0;
+    p.merge_siblings = 1;
     p.user_perm = nullptr;
     return p;
 }
@@ -258,6 +259,7 @@ static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::v
     so.user_perm = h->prm.user_perm;
     so.block_width = h->prm.block_width;
     so.max_block_entries = kMaxPanel;
+    so.merge_siblings = h->prm.merge_siblings ? 1 : 0;
     const std::string serr = build_symbolic(n, arow, acol, so, h->S);
     if (!serr.empty()) return fail(h, SDPC_E_PATTERN, serr);
     const Symbolic &S = h->S;
@@ -550,6 +552,67 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         am_ptr[q] = int64_t(am_sidx.size());
     }
     h->kq_ptr_h = kq_ptr;
+    // column-compressed general form: strict triangle with the smaller column union,
+    // the diagonal, and the rows of every A_q (full symmetric) for the sparse products
+    std::vector<int> ccol, ds_v, seg_q, seg_row, seg_col;
+    std::vector<int64_t> seg_ptr(1, 0);
+    std::vector<double> ucat, dmat, seg_val;
+    if (!had && m > 0) {
+        std::vector<uint8_t> in_up(n, 0), in_lo(n, 0), in_d(n, 0);
+        for (int k = 1; k <= m; ++k)
+            for (auto &e : ent[k]) {
+                if (e.pi != e.pj) {
+                    in_up[e.pi] = 1;   // upper entry (pj, pi) sits in column pi
+                    in_lo[e.pj] = 1;   // lower entry (pi, pj) sits in column pj
+                } else {
+                    in_d[e.pi] = 1;
+                }
+            }
+        int nup = 0, nlo = 0;
+        for (int i = 0; i < n; ++i) { nup += in_up[i]; nlo += in_lo[i]; }
+        const bool use_up = nup <= nlo;
+        std::vector<int> cpos(n, -1), dpos(n, -1);
+        for (int i = 0; i < n; ++i)
+            if (use_up ? in_up[i] : in_lo[i]) { cpos[i] = int(ccol.size()); ccol.push_back(i); }
+        for (int i = 0; i < n; ++i)
+            if (in_d[i]) { dpos[i] = int(ds_v.size()); ds_v.push_back(i); }
+        const int64_t nc = int64_t(ccol.size()), nds = int64_t(ds_v.size());
+        const int64_t ucat_len = int64_t(n) * m * nc;
+        const int64_t budget = int64_t(1) << 27;   // doubles per work block (1 GiB)
+        if (ucat_len <= budget && nds * m <= budget && int64_t(n) * nc * (m + 1) <= budget) {
+            d.cc = 1;
+            d.nc = int(nc);
+            d.nds = int(nds);
+            ucat.assign(size_t(std::max<int64_t>(ucat_len, 1)), 0.0);
+            dmat.assign(size_t(std::max<int64_t>(nds * m, 1)), 0.0);
+            for (int k = 1; k <= m; ++k) {
+                std::vector<std::pair<std::pair<int, int>, double>> full;   // ((row, col), v), both triangles
+                for (auto &e : ent[k]) {
+                    if (e.pi != e.pj) {
+                        const int r = use_up ? e.pj : e.pi, c = use_up ? e.pi : e.pj;
+                        ucat[size_t(r) + size_t(n) * (size_t(k - 1) * nc + cpos[c])] += e.v;
+                        full.push_back({{e.pi, e.pj}, e.v});
+                        full.push_back({{e.pj, e.pi}, e.v});
+                    } else {
+                        dmat[size_t(dpos[e.pi]) + size_t(nds) * (k - 1)] += e.v;
+                        full.push_back({{e.pi, e.pi}, e.v});
+                    }
+                }
+                std::sort(full.begin(), full.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+                for (size_t t = 0; t < full.size(); ++t) {
+                    if (t == 0 || full[t].first.first != full[t - 1].first.first) {
+                        if (t > 0) seg_ptr.push_back(int64_t(seg_col.size()));
+                        seg_q.push_back(k - 1);
+                        seg_row.push_back(full[t].first.first);
+                    }
+                    seg_col.push_back(full[t].first.second);
+                    seg_val.push_back(full[t].second);
+                }
+                if (!full.empty()) seg_ptr.push_back(int64_t(seg_col.size()));
+            }
+            d.nseg = int64_t(seg_q.size());
+        }
+    }
     // aggregate pattern, full symmetric CSC with slots
     std::vector<int64_t> ag_cptr(n + 1, 0);
     std::vector<int> ag_row, ag_slot;
@@ -659,6 +722,17 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.zg_mma, zg_mma));
     TRY(upload(h, &d.zg_col, zg_col));
     TRY(upload(h, &d.pos, S.pos));
+    if (d.cc) {
+        TRY(upload(h, &d.ccol, ccol));
+        TRY(upload(h, &d.ucat, ucat));
+        TRY(upload(h, &d.ds, ds_v));
+        TRY(upload(h, &d.dmat, dmat));
+        TRY(upload(h, &d.seg_q, seg_q));
+        TRY(upload(h, &d.seg_row, seg_row));
+        TRY(upload(h, &d.seg_ptr, seg_ptr));
+        TRY(upload(h, &d.seg_col, seg_col));
+        TRY(upload(h, &d.seg_val, seg_val));
+    }
     // ---- workspace
     const size_t ns = size_t(S.nslot), nn = size_t(n) * n;
     h->ldb = int64_t(m) + 1;   // row m carries the SCE right-hand side through the factorisation
@@ -697,6 +771,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->ydw_dual, wave_chol_work_doubles(d)));
     TRY(dalloc(h, &h->part, std::max(size_t(2) * dX_chunks(d) * ns, size_t(rhs_had_parts(d)) * n)));
     TRY(dalloc(h, &h->flags, kCand + 8));
+    if (d.cc) TRY(dalloc(h, &h->ccwork, cc_work_doubles(d)));
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), h->st));
@@ -873,6 +948,8 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     HIPCHK(h, hipEventRecord(h->evs[3], st));
     if (d.hadamard)
         launch_scm_hadamard(d, h->Xh, h->Yi, B, ldb, st);
+    else if (d.cc)
+        launch_scm_cc(d, h->Xh, h->Yi, h->W, h->ccwork, B, ldb, st);
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
     HIPCHK(h, hipEventRecord(h->evs[4], st));
@@ -947,24 +1024,29 @@ void fill_result(sdpc_handle *h, const IterInfo &it, sdpc_result *res) {
     res->device_bytes = h->bytes;
 }
 
-// One iteration.  *done = true when the stopping test held (no update).
-sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done) {
+// One iteration.  *done = true when the stopping test held (no update).  With
+// mu_target > 0 the step is a centring step instead: the direction aims at the
+// point of the central path with X Y = mu_target I (the target beta mu of Step 2
+// replaced by mu_target), and the stopping test is not applied.
+sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_target = 0.0) {
     DevStruct &d = h->d;
     hipStream_t st = h->st;
     IterInfo it;
     TRY(read_metrics(h, it));
-    *done = it.stop;
-    if (it.stop) {
+    *done = it.stop && !(mu_target > 0.0);
+    if (*done) {
         fill_result(h, it, res);
         return SDPC_OK;
     }
-    const double bm = it.beta * it.mu;
+    const double bm = (mu_target > 0.0) ? mu_target : it.beta * it.mu;
     TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false, true));
     hipEvent_t *ev = h->ev;
     HIPCHK(h, hipEventRecord(ev[0], st));
     // right-hand side: g = b - beta mu A(Y^{-1}) + A(X^ G Y^{-1})
     if (d.hadamard)
         launch_rhs_hadamard(d, h->G, h->Xh, h->Yi, h->part, h->hcol, st);
+    else if (d.cc)
+        launch_scm_cc_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->ccwork, h->hcol, st);
     else
         launch_scm_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
     launch_rhs(d, h->Yi, h->hcol, bm, h->g, st);
@@ -1229,6 +1311,74 @@ sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
     if (fl[0]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
     h->xside_ready = true;   // Lhat and its diagonal inverses belong to the current X
     return SDPC_OK;
+}
+
+sdpc_status sdpc_center(sdpc_handle *h, double mu, int32_t max_steps, double tol, int32_t *steps,
+                        double *last_rel_step) {
+    if (!h || !(mu > 0.0) || !std::isfinite(mu) || max_steps < 1 || !(tol >= 0.0))
+        return h ? fail(h, SDPC_E_ARG, "bad sdpc_center arguments (need mu > 0, max_steps >= 1, tol >= 0)")
+                 : SDPC_E_ARG;
+    const int m = h->m;
+    std::vector<double> dz(size_t(std::max(m, 1))), z(size_t(std::max(m, 1)));
+    sdpc_status s = SDPC_OK;
+    double rel = INFINITY;
+    int k = 0;
+    while (k < max_steps) {
+        bool done = false;
+        s = step_impl(h, nullptr, &done, mu);
+        if (s != SDPC_OK) break;
+        ++k;
+        // how far z moved: gamma alpha_d dz relative to z
+        if (m > 0) {
+            HIPCHK(h, hipMemcpy(dz.data(), h->dz, size_t(m) * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(z.data(), h->z, size_t(m) * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        double mdz = 0.0, mz = 1.0;
+        for (int i = 0; i < m; ++i) {
+            mdz = std::max(mdz, std::fabs(dz[i]));
+            mz = std::max(mz, std::fabs(z[i]));
+        }
+        rel = h->prm.gamma * h->last_alpha[1] * mdz / mz;
+        if (rel <= tol) break;
+    }
+    if (steps) *steps = k;
+    if (last_rel_step) *last_rel_step = rel;
+    return s;
+}
+
+sdpc_status sdpc_adjoint(sdpc_handle *h, const double *d_GL_E, const double *d_dLdz, double *d_gb,
+                         double *d_gC_E) {
+    if (!h || !d_GL_E || !d_gb || !d_gC_E) return h ? fail(h, SDPC_E_ARG, "bad sdpc_adjoint arguments") : SDPC_E_ARG;
+    DevStruct &d = h->d;
+    hipStream_t st = h->st;
+    const int m = d.m;
+    // B, X^ and Y^{-1} of the current iterate
+    TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false));
+    // h_p = A_p . (X^ G_L Y^{-1}), then lambda = B^{-1} (h + dL/dz) by the SCM Cholesky
+    // with the right-hand side riding along as row m, and the backward substitution
+    if (d.hadamard)
+        launch_rhs_hadamard(d, d_GL_E, h->Xh, h->Yi, h->part, h->hcol, st);
+    else if (d.cc)
+        launch_scm_cc_extra_column(d, d_GL_E, h->Xh, h->Yi, h->W, h->ccwork, h->hcol, st);
+    else
+        launch_scm_extra_column(d, d_GL_E, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
+    launch_add(m, h->hcol, d_dLdz, h->g, st);
+    HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
+    launch_set_row(m, h->g, h->B + m, h->ldb, st);
+    launch_potrf_rows(m, m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    launch_potrs_bwd(m, h->B, h->ldb, h->B + m, h->ldb, d_gb, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
+    // dL/dA_0 = sym(X^ (sum_k lambda_k A_k - G_L) Y^{-1}) on E: the dX kernels with
+    // M = G_L - sum_k lambda_k A_k, no beta mu term and a zero Xbar give -sym(X^ M Y^{-1})
+    launch_assemble(d, d_gb, 0.0, 1.0, d_GL_E, h->G, st);
+    launch_zcol(d, h->Xh, h->G, h->W, st);
+    HIPCHK(h, hipMemsetAsync(h->Xn, 0, size_t(d.nslot) * sizeof(double), st));
+    launch_dX_blocked(d, h->W, h->Yi, h->Xn, 0.0, h->part, d_gC_E, st);
+    HIPCHK(h, hipGetLastError());
+    h->metrics_ready = false;   // G was used as workspace: the next step recomputes it
+    int fl[kCand + 8];
+    HIPCHK(h, hipMemcpyAsync(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    return check_flags(h, true, fl);
 }
 
 sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5) {

@@ -13,6 +13,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// out = a + b (b may be null: out = a)
+__global__ void k_add(int64_t len, const double *__restrict__ a, const double *__restrict__ b,
+                      double *__restrict__ out) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = b ? a[i] + b[i] : a[i];
+}
+
 __global__ void k_assemble(int64_t nslot, const int64_t *__restrict__ ptr, const int *__restrict__ kk,
                            const double *__restrict__ val, const double *__restrict__ y, double a0,
                            double c1, const double *__restrict__ in1, double *__restrict__ out) {
@@ -201,6 +208,11 @@ void launch_axpy_checked(int64_t len, const double *x, const double *dx, const d
                          double scale, const int *flags, int nflag, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy_checked, dim3(grid_for(len)), dim3(kThreads), 0, st, len, x, dx, alpha, alpha2, scale,
                        flags, nflag, out);
+}
+
+void launch_add(int64_t len, const double *a, const double *b, double *out, hipStream_t st) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_add, dim3(grid_for(len)), dim3(kThreads), 0, st, len, a, b, out);
 }
 
 void launch_unpermute(const DevStruct &d, const double *in, double *out, hipStream_t st) {

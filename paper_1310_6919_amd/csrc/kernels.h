@@ -116,6 +116,22 @@ struct DevStruct {
     int nzg_mma = 0, nzg_col = 0;
     const int *zg_mma = nullptr;        // groups on the MFMA path
     const int *zg_col = nullptr;        // groups on the column path
+    // general path, column-compressed form (k_scm_cc.hip): A_q = U_q + U_q^T + D_q with
+    // U_q the strict triangle (upper or lower, whichever has the smaller column union C
+    // over all q) and D_q the diagonal
+    int cc = 0;                         // 1: the column-compressed form is used
+    int nc = 0;                         // |C|
+    const int *ccol = nullptr;          // nc positions
+    const double *ucat = nullptr;       // n x (m nc) column-major: U_1(:, C) .. U_m(:, C)
+    int nds = 0;                        // positions holding a diagonal entry of some A_q
+    const int *ds = nullptr;            // nds
+    const double *dmat = nullptr;       // nds x m column-major: D_q(ds[i])
+    int64_t nseg = 0;                   // rows of A_1 .. A_m (full symmetric), in order
+    const int *seg_q = nullptr;         // nseg
+    const int *seg_row = nullptr;       // nseg
+    const int64_t *seg_ptr = nullptr;   // nseg + 1: entries (seg_col, seg_val) of each row
+    const int *seg_col = nullptr;
+    const double *seg_val = nullptr;
     const int *pos = nullptr;           // n: position (elimination order) of every original index
     int solve_generic = 0;              // 1: the substitutions always take the generic walk
 };
@@ -133,6 +149,8 @@ void launch_metrics(const DevStruct &d, const double *X, const double *Y, const 
 // alpha2[0] when given) are positive, else out = x; out may be x
 void launch_axpy_checked(int64_t len, const double *x, const double *dx, const double *alpha, const double *alpha2,
                          double scale, const int *flags, int nflag, double *out, hipStream_t st);
+// out = a + b elementwise (b == nullptr: out = a)
+void launch_add(int64_t len, const double *a, const double *b, double *out, hipStream_t st);
 // out(i, j) = in(pos[i], pos[j]) for dense n x n column-major matrices
 void launch_unpermute(const DevStruct &d, const double *in, double *out, hipStream_t st);
 void launch_init_point(const DevStruct &d, double lambda, double *X, double *Y, double *z,
@@ -207,6 +225,15 @@ void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, doubl
 int rhs_had_parts(const DevStruct &d);
 void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *Xh, const double *Yi,
                          double *part, double *hcol, hipStream_t st);
+// column-compressed general SCM (d.cc): B lower (ldb) from X^ and Y^{-1}; H: n x n
+// workspace; work: cc_work_doubles(d), which keeps the blocks the extra column reuses
+size_t cc_work_doubles(const DevStruct &d);
+void launch_scm_cc(const DevStruct &d, const double *Xh, const double *Yi, double *H, double *work, double *B,
+                   int64_t ldb, hipStream_t st);
+// col[p] = A_p . (X^ M Y^{-1}) for M on the aggregate pattern, after launch_scm_cc on
+// the same X^ and Y^{-1}; Z: n x n workspace
+void launch_scm_cc_extra_column(const DevStruct &d, const double *Mvec, const double *Xh, const double *Yi,
+                                double *Z, double *work, double *col, hipStream_t st);
 // dX on E from Z = X^ dY (column-major): part holds 2 * dX_chunks * nslot doubles
 int dX_chunks(const DevStruct &d);
 void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, const double *Xbar,

@@ -223,8 +223,14 @@ std::string build_symbolic(int n, const std::vector<int> &arow, const std::vecto
         size_t q = p + 1;
         while (q < pieces.size()) {
             const int a = pieces[q].first, e = pieces[q].second;
-            if (a != end || S.parent[end - 1] != a || e - F > W) break;
+            if (a != end || e - F > W) break;
+            // a chain (the next piece starts at the parent of the block's last column), or,
+            // with merge_siblings, the next subtree in postorder when the tail rows do not
+            // grow (the columns share no entries: explicit zeros, E unchanged)
+            const bool chain = S.parent[end - 1] == a;
+            if (!chain && !opt.merge_siblings) break;
             std::vector<int> t2 = own_tail(F, e, {});
+            if (!chain && t2.size() > tail.size()) break;
             if (int64_t(e - F + t2.size()) * (e - F) > opt.max_block_entries) break;
             end = e;
             tail = t2;
@@ -260,7 +266,11 @@ std::string build_symbolic(int n, const std::vector<int> &arow, const std::vecto
     for (int b = 0; b < S.nb; ++b) {
         const int last = S.bl_first[b + 1] - 1;
         S.bl_parent[b] = S.parent[last] >= 0 ? S.col_block[S.parent[last]] : -1;
-        S.bl_subfirst[b] = last - sub[last] + 1;
+        // the block's columns may head several subtrees (merged siblings): the smallest
+        // column of their union, an interval in postorder
+        int sf = last - sub[last] + 1;
+        for (int j = S.bl_first[b]; j < last; ++j) sf = std::min(sf, j - sub[j] + 1);
+        S.bl_subfirst[b] = sf;
     }
     // ---- exact-E mask of the storage
     S.isE.assign(size_t(S.nslot), 0);

@@ -9,8 +9,9 @@
 //   cliques  the fundamental supernodes.  Algorithm 1 and the clique-wise
 //            step length run on these (exact E).
 //   blocks   storage panels: consecutive supernodes along an elimination-tree
-//            chain merged up to a width limit (explicit zeros allowed), or a
-//            wide supernode cut into pieces.  Every column's exact structure
+//            chain, or consecutive sibling subtrees whose rows below the block
+//            do not grow, merged up to a width limit (explicit zeros allowed),
+//            or a wide supernode cut into pieces.  Every column's exact structure
 //            lies inside its block's row list, so factors stored this way are
 //            the same matrices; the zeros only pad the dense panel work.
 #pragma once
@@ -53,6 +54,7 @@ struct SymbolicOptions {
     const int32_t *user_perm = nullptr;
     int block_width = 32;
     int max_block_entries = 8192;     // h * w limit of one panel (doubles)
+    int merge_siblings = 1;           // also merge consecutive sibling subtrees whose tail rows do not grow
 };
 
 // Builds everything from the lower-triangle aggregate pattern (original

@@ -22,7 +22,7 @@ SDPC_OK, SDPC_E_ARG, SDPC_E_PATTERN, SDPC_E_NOT_PD, SDPC_E_HIP, SDPC_E_MAXITER, 
 EXPORTS = ["sdpc_default_params", "sdpc_analyze", "sdpc_create", "sdpc_solve", "sdpc_reset", "sdpc_step", "sdpc_scm",
            "sdpc_potrf", "sdpc_get_pattern", "sdpc_get_cliques", "sdpc_get_solution", "sdpc_set_state",
            "sdpc_get_factors", "sdpc_get_dense", "sdpc_complete_dense", "sdpc_get_direction", "sdpc_get_scm_timing",
-           "sdpc_potrf_static", "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
+           "sdpc_center", "sdpc_adjoint", "sdpc_potrf_static", "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
 
 
 class sdpc_problem(C.Structure):
@@ -36,7 +36,7 @@ class sdpc_params(C.Structure):
                 ("beta_infeas", C.c_double), ("gamma", C.c_double), ("lambda0", C.c_double),
                 ("max_iter", C.c_int32), ("ordering", C.c_int32), ("block_width", C.c_int32),
                 ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("solve_kernel", C.c_int32),
-                ("factorization", C.c_int32), ("reserved_", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+                ("factorization", C.c_int32), ("merge_siblings", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
 
 
 class sdpc_analysis(C.Structure):
@@ -92,6 +92,8 @@ def load():
         "sdpc_complete_dense": (I32, [VP, VP]),
         "sdpc_get_direction": (I32, [VP, VP, VP, VP, P(D)]),
         "sdpc_get_scm_timing": (I32, [VP, P(D)]),
+        "sdpc_center": (I32, [VP, D, I32, D, P(I32), P(D)]),
+        "sdpc_adjoint": (I32, [VP, VP, VP, VP, VP]),
         "sdpc_potrf_static": (I32, [VP, I64, I32, VP, VP]),
         "sdpc_status_string": (C.c_char_p, [I32]),
         "sdpc_last_error": (C.c_char_p, [VP]),
@@ -306,6 +308,20 @@ class Handle:
         al = (C.c_double * 2)()
         self._check(self.lib.sdpc_get_direction(self.h, _ptr(dz), _ptr(dX), _ptr(dY), al), "sdpc_get_direction")
         return dz, dX, dY, (al[0], al[1])
+
+    def sdpc_center(self, mu, max_steps=60, tol=1e-14):
+        """Newton steps toward the mu-central point; returns (steps, last relative z step)."""
+        k = C.c_int32()
+        rel = C.c_double()
+        self._check(self.lib.sdpc_center(self.h, float(mu), int(max_steps), float(tol), C.byref(k), C.byref(rel)),
+                    "sdpc_center")
+        return int(k.value), float(rel.value)
+
+    def sdpc_adjoint(self, GL_E, dLdz=None):
+        """(dL/db, dL/dA_0 as an E-vector) at the current (central) iterate."""
+        gb, gC = self._empty(self.m), self._empty(self.nslot)
+        self._check(self.lib.sdpc_adjoint(self.h, _ptr(GL_E), _ptr(dLdz), _ptr(gb), _ptr(gC)), "sdpc_adjoint")
+        return gb, gC
 
     def sdpc_get_scm_timing(self):
         ms = (C.c_double * 5)()

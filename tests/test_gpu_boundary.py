@@ -233,3 +233,42 @@ def test_solves_are_bitwise_reproducible(name):
         assert o[0] == out[0][0] and o[1] == out[0][1] and o[2] == out[0][2]
         for a, b in zip(o[3:], out[0][3:]):
             assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------- storage blocks
+def _ktree_case():
+    prob = sdpgen.maxcut_ktree_batch(4, 0)[1]
+    return prob, {"user_perm": np.arange(prob.n)[::-1].astype(np.int32)}
+
+
+@pytest.mark.parametrize("name", ["normmin", "normmin_wide", "ktree"])
+def test_sibling_merged_blocks_match_chain_blocks(name):
+    """merge_siblings only adds explicit zeros to the storage panels: the Schur
+    complement matrix and whole solves agree with the chain-only blocks, and B
+    with the oracle."""
+    if name == "ktree":
+        prob, kw = _ktree_case()
+    elif name == "normmin_wide":
+        prob, kw = sdpgen.normmin(300, 10, 12, 2), {}
+    else:
+        prob, kw = CASES[name](), {}
+    rng = np.random.default_rng(31)
+    Xfull, Y = _state(prob, rng)
+    Bs, res = [], []
+    for ms in (0, 1):
+        h = _create(prob, merge_siblings=ms, gap_tol=1e-8, feas_tol=1e-8, **kw)
+        Bs.append(np.tril(host(h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y))))))
+        res.append(h.sdpc_solve())
+        _, _, perm = h.sdpc_get_pattern()
+        h.close()
+    assert rel_err(Bs[1], Bs[0]) <= 1e-12
+    # the oracle's completion on the E of the library's elimination order
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols, perm)
+    Xh = ch.unpermute(oracle.maxdet_complete(ch, np.where(ch.E_mask(), ch.permute(Xfull), 0.0)))
+    Bref = oracle.dense_scm(oracle.scm.problem_mats(prob), Xh, np.linalg.inv(Y))
+    assert rel_err(Bs[1], np.tril(Bref)) <= 1e-10
+    assert res[0]["status"] == 0 and res[1]["status"] == 0
+    assert res[0]["iters"] == res[1]["iters"]
+    o0, o1 = [(r["pobj"] + r["dobj"]) / 2 for r in res]
+    assert abs(o1 - o0) <= 1e-9 * max(1.0, abs(o0))
