@@ -635,10 +635,10 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         }
     }
     // the same pattern by groups of 32 columns (row union and a slot per union row and
-    // column); small unions go to the MFMA path of X^ M
+    // column) for the MFMA products X^ M
     const int nzg = (n + 31) / 32;
     std::vector<int64_t> zg_ptr(nzg + 1, 0);
-    std::vector<int> zg_rows, zg_slot, zg_mma, zg_col;
+    std::vector<int> zg_rows, zg_slot, zg_mma;
     for (int g = 0; g < nzg; ++g) {
         const int c0 = 32 * g, c1 = std::min(n, c0 + 32);
         std::vector<int> u;
@@ -647,11 +647,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         std::sort(u.begin(), u.end());
         u.erase(std::unique(u.begin(), u.end()), u.end());
         const int K = (int(u.size()) + 3) / 4 * 4;
-        if (K > kZmRows) {
-            zg_col.push_back(g);
-            zg_ptr[g + 1] = zg_ptr[g];
-            continue;
-        }
         zg_mma.push_back(g);
         const size_t base = zg_slot.size();
         zg_slot.resize(base + size_t(K) * 32, -1);
@@ -665,7 +660,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     }
     d.nzg = nzg;
     d.nzg_mma = int(zg_mma.size());
-    d.nzg_col = int(zg_col.size());
     // ---- uploads
     TRY(upload(h, &d.bl_first, S.bl_first));
     TRY(upload(h, &d.bl_rptr, S.bl_rptr));
@@ -720,7 +714,6 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.zg_rows, zg_rows));
     TRY(upload(h, &d.zg_slot, zg_slot));
     TRY(upload(h, &d.zg_mma, zg_mma));
-    TRY(upload(h, &d.zg_col, zg_col));
     TRY(upload(h, &d.pos, S.pos));
     if (d.cc) {
         TRY(upload(h, &d.ccol, ccol));

@@ -126,52 +126,15 @@ k_dX(int64_t nslot, int n, const int *__restrict__ slot_row, const int *__restri
 
 typedef double d4 __attribute__((ext_vector_type(4)));   // one MFMA accumulator
 
-// Z = X^ M, column-major (Z(p, c) at p + n c), for the columns of the listed groups
-// of 32; the entries of column c of M are uniform across the workgroup, the reads of
-// X^ are coalesced over p
-__global__ void __launch_bounds__(256)
-k_zcol(int n, const int *__restrict__ groups, const int64_t *__restrict__ cptr, const int *__restrict__ rows,
-       const int *__restrict__ slots, const double *__restrict__ Mvec, const double *__restrict__ Xh,
-       double *__restrict__ Z) {
-    const int g = groups[blockIdx.y];
-    for (int c = 32 * g + int(blockIdx.x); c < min(n, 32 * g + 32); c += gridDim.x) {
-        const int64_t t0 = cptr[c], t1 = cptr[c + 1];
-        for (int p = threadIdx.x; p < n; p += blockDim.x) {
-            double s = 0.0;
-            for (int64_t t = t0; t < t1; ++t) s += Mvec[slots[t]] * Xh[p + int64_t(n) * rows[t]];
-            Z[p + int64_t(n) * c] = s;
-        }
-    }
-}
-
-// Max-cut form: h_p = A_p . (X^ M Y^{-1}) = (X^ M Y^{-1})(p, p) = sum_c (X^ M)(p, c) Y^{-1}(p, c)
-// (Y^{-1} symmetric).  Partial sums over the 32 columns of each listed group, in
-// part[group][p]; X^ M is never stored.
-__global__ void __launch_bounds__(256)
-k_rhs_had_partial(int n, const int *__restrict__ groups, const int64_t *__restrict__ cptr,
-                  const int *__restrict__ rows, const int *__restrict__ slots, const double *__restrict__ Mvec,
-                  const double *__restrict__ Xh, const double *__restrict__ Yi, double *__restrict__ part) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = groups[blockIdx.y];
-    const int c0 = 32 * g;
-    const int c1 = min(n, c0 + 32);
-    if (p >= n) return;
-    double acc = 0.0;
-    for (int c = c0; c < c1; ++c) {
-        double z = 0.0;
-        for (int64_t t = cptr[c]; t < cptr[c + 1]; ++t) z += Mvec[slots[t]] * Xh[p + int64_t(n) * rows[t]];
-        acc += z * Yi[p + int64_t(n) * c];
-    }
-    part[int64_t(g) * n + p] = acc;
-}
-
-// The same two products for a group of 32 columns whose rows form a small union U
-// (|U| <= kZmRows): Z(P, G) = X^(P, U) M(U, G) is a dense product on the FP64 MFMA,
-// with M(U, G) gathered into LDS.  It is formed transposed, Z^T = M^T X^T (lane l
+// The same two products for a group of 32 columns whose rows form the union U:
+// Z(P, G) = X^(P, U) M(U, G) is a dense product on the FP64 MFMA, with M(U, G)
+// gathered into LDS kZmRows rows at a time.  It is formed transposed, Z^T = M^T X^T (lane l
 // supplies A(l % 16, l / 16) and B(l / 16, l % 16); element r of the result is
 // C(4 r + l / 16, l % 16)), so 16 lanes hold 16 consecutive rows p of one column:
 // coalesced reads of X^ and Y^{-1} and writes of Z.  Each workgroup takes 64 rows
-// (16 per wave).  RHS: h partials as k_rhs_had_partial; otherwise Z is stored.
+// (16 per wave).  RHS: the partial sums over the group's columns of
+// (X^ M)(p, c) Y^{-1}(p, c), whose total is h_p = (X^ M Y^{-1})(p, p) in the max-cut
+// form; otherwise Z is stored.
 template <bool RHS>
 __global__ void __launch_bounds__(256)
 k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_ptr, const int *__restrict__ zg_rows,
@@ -181,24 +144,29 @@ k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_p
     __shared__ int Ur[kZmRows];
     const int g = groups[blockIdx.y];
     const int64_t u0 = zg_ptr[g];
-    const int K = int(zg_ptr[g + 1] - u0);   // a multiple of 4, <= kZmRows
-    for (int idx = threadIdx.x; idx < K * 32; idx += blockDim.x) {
-        const int sl = zg_slot[32 * u0 + idx];
-        Mb[(idx / 32) * 33 + idx % 32] = (sl >= 0) ? Mvec[sl] : 0.0;
-    }
-    for (int k = threadIdx.x; k < K; k += blockDim.x) Ur[k] = zg_rows[u0 + k];
-    __syncthreads();
+    const int K = int(zg_ptr[g + 1] - u0);   // a multiple of 4
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     const int p = 64 * blockIdx.x + 16 * wv + li;
     const int pc = min(p, n - 1);   // clamped: loads stay in range
     d4 acc[2];
     acc[0] = acc[1] = d4{0.0, 0.0, 0.0, 0.0};
+    // the union rows in chunks of kZmRows, each chunk of M(U, G) staged in LDS
+    for (int kb = 0; kb < K; kb += kZmRows) {
+        const int KK = min(kZmRows, K - kb);
+        __syncthreads();   // the previous chunk has been consumed
+        for (int idx = threadIdx.x; idx < KK * 32; idx += blockDim.x) {
+            const int sl = zg_slot[32 * (u0 + kb) + idx];
+            Mb[(idx / 32) * 33 + idx % 32] = (sl >= 0) ? Mvec[sl] : 0.0;
+        }
+        for (int k = threadIdx.x; k < KK; k += blockDim.x) Ur[k] = zg_rows[u0 + kb + k];
+        __syncthreads();
 #pragma unroll 4
-    for (int ks = 0; ks < K / 4; ++ks) {
-        const int k = 4 * ks + lk;
-        const double x = Xh[pc + int64_t(n) * Ur[k]];
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[k * 33 + li], x, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[k * 33 + 16 + li], x, acc[1], 0, 0, 0);
+        for (int ks = 0; ks < KK / 4; ++ks) {
+            const int k = 4 * ks + lk;
+            const double x = Xh[pc + int64_t(n) * Ur[k]];
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[k * 33 + li], x, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(Mb[k * 33 + 16 + li], x, acc[1], 0, 0, 0);
+        }
     }
     if (RHS) {
         double sacc = 0.0;
@@ -370,9 +338,6 @@ void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, doubl
     if (d.nzg_mma > 0)
         hipLaunchKernelGGL(k_zm_mma<false>, dim3((d.n + 63) / 64, d.nzg_mma), dim3(256), 0, st, d.n, d.zg_mma,
                            d.zg_ptr, d.zg_rows, d.zg_slot, Mvec, Xh, (const double *)nullptr, Z);
-    if (d.nzg_col > 0)
-        hipLaunchKernelGGL(k_zcol, dim3(32, d.nzg_col), dim3(256), 0, st, d.n, d.zg_col, d.ag_cptr, d.ag_row,
-                           d.ag_slot, Mvec, Xh, Z);
 }
 
 int rhs_had_parts(const DevStruct &d) { return d.nzg; }
@@ -383,9 +348,6 @@ void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *X
     if (d.nzg_mma > 0)
         hipLaunchKernelGGL(k_zm_mma<true>, dim3((d.n + 63) / 64, d.nzg_mma), dim3(256), 0, st, d.n, d.zg_mma,
                            d.zg_ptr, d.zg_rows, d.zg_slot, Mvec, Xh, Yi, part);
-    if (d.nzg_col > 0)
-        hipLaunchKernelGGL(k_rhs_had_partial, dim3((d.n + 255) / 256, d.nzg_col), dim3(256), 0, st, d.n, d.zg_col,
-                           d.ag_cptr, d.ag_row, d.ag_slot, Mvec, Xh, Yi, part);
     hipLaunchKernelGGL(k_sum_partials, dim3(grid_cap(d.m, 256)), dim3(256), 0, st, d.m, nparts,
                        (const double *)part, d.had_pos, hcol);
 }

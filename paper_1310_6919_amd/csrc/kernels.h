@@ -107,15 +107,14 @@ struct DevStruct {
     const int *ag_slot = nullptr;
     // the same pattern by groups of 32 consecutive columns: the union of the rows of a
     // group (padded to a multiple of 4) and, per union row and column of the group, the
-    // slot of the entry (-1: none).  Groups whose union has at most kZmRows rows are
-    // formed as small dense products on the MFMA; the others column by column.
+    // slot of the entry (-1: none); every group is a dense product on the MFMA over its
+    // union, kZmRows union rows at a time.
     int nzg = 0;                        // ceil(n / 32)
     const int64_t *zg_ptr = nullptr;    // nzg + 1: offsets into zg_rows (zg_slot: 32 per row)
     const int *zg_rows = nullptr;
     const int *zg_slot = nullptr;
-    int nzg_mma = 0, nzg_col = 0;
+    int nzg_mma = 0;
     const int *zg_mma = nullptr;        // groups on the MFMA path
-    const int *zg_col = nullptr;        // groups on the column path
     // general path, column-compressed form (k_scm_cc.hip): A_q = U_q + U_q^T + D_q with
     // U_q the strict triangle (upper or lower, whichever has the smaller column union C
     // over all q) and D_q the diagonal
