@@ -755,7 +755,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->pflags_b, size_t(potrf_flag_count(m))));
     TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->scal, 16));
-    TRY(dalloc(h, &h->mwork, metrics_work_doubles()));
+    TRY(dalloc(h, &h->mwork, metrics_work_doubles(m)));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));

@@ -90,15 +90,20 @@ k_contract(int m, int q0, const int64_t *__restrict__ am_ptr, const int64_t *__r
     }
 }
 
+// g_p = b_p - beta mu A_p . Y^{-1} + h_p: one wave per constraint, its entries split
+// over the lanes and summed in a fixed order
 __global__ void __launch_bounds__(256)
 k_rhs(int m, int n, const int64_t *__restrict__ con_ptr, const int *__restrict__ con_pi,
       const int *__restrict__ con_pj, const double *__restrict__ con_val, const double *__restrict__ b,
       const double *__restrict__ Yi, const double *__restrict__ hcol, double beta_mu, double *__restrict__ g) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < m; p += waves) {
         double ay = 0.0;
-        for (int64_t t = con_ptr[p + 1]; t < con_ptr[p + 2]; ++t)
-            ay += con_val[t] * Yi[con_pi[t] + int64_t(n) * con_pj[t]];
-        g[p] = b[p] - beta_mu * ay + hcol[p];
+        for (int64_t t = con_ptr[p + 1] + lane; t < con_ptr[p + 2]; t += 64)
+            ay = fma(con_val[t], Yi[con_pi[t] + int64_t(n) * con_pj[t]], ay);
+        for (int o = 32; o > 0; o >>= 1) ay += __shfl_xor(ay, o, 64);
+        if (lane == 0) g[p] = b[p] - beta_mu * ay + hcol[p];
     }
 }
 
@@ -364,7 +369,7 @@ void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, co
 }
 
 void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g, hipStream_t st) {
-    hipLaunchKernelGGL(k_rhs, dim3(grid_cap(d.m, 256)), dim3(256), 0, st, d.m, d.n, d.con_ptr, d.con_pi, d.con_pj,
+    hipLaunchKernelGGL(k_rhs, dim3(grid_cap(d.m, 4)), dim3(256), 0, st, d.m, d.n, d.con_ptr, d.con_pi, d.con_pj,
                        d.con_val, d.b, Yi, h, beta_mu, g);
 }
 

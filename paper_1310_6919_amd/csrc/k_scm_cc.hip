@@ -147,6 +147,50 @@ k_cc_q(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *__
     }
 }
 
+// The same for |C| <= 16 with the lanes over the entries of the segment (long rows
+// are not one serial chain): every lane keeps |C| partial sums of each product,
+// reduced over the wave in a fixed order.
+__global__ void __launch_bounds__(256)
+k_cc_q16(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *__restrict__ seg_row,
+         const int64_t *__restrict__ seg_ptr, const int *__restrict__ seg_col, const double *__restrict__ seg_val,
+         const int *__restrict__ seg_slot, const double *__restrict__ Mvec, int qfix, const double *__restrict__ YC,
+         const double *__restrict__ XC, double *__restrict__ Q, double *__restrict__ Qp) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x >> 6) + (threadIdx.x >> 6); s < nseg; s += waves) {
+        const int q = seg_q ? seg_q[s] : qfix;
+        const int i = seg_row ? seg_row[s] : int(s);
+        const int64_t t0 = seg_ptr[s], t1 = seg_ptr[s + 1];
+        double ay[16], ax[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) ay[c] = ax[c] = 0.0;
+        for (int64_t t = t0 + lane; t < t1; t += 64) {
+            const int j = seg_col[t];
+            const double v = seg_slot ? Mvec[seg_slot[t]] : seg_val[t];
+            const double *yc = YC + int64_t(nc) * j, *xc = XC + int64_t(nc) * j;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < nc) {
+                    ay[c] = fma(v, yc[c], ay[c]);
+                    ax[c] = fma(v, xc[c], ax[c]);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            if (c >= nc) break;
+            double y = ay[c], x = ax[c];
+            for (int o = 32; o > 0; o >>= 1) {
+                y += __shfl_xor(y, o, 64);
+                x += __shfl_xor(x, o, 64);
+            }
+            if (lane == 0) {
+                Q[int64_t(q) * n * nc + i + int64_t(n) * c] = y;
+                Qp[int64_t(q) * n * nc + i + int64_t(n) * c] = x;
+            }
+        }
+    }
+}
+
 // H(a, i) = X^(ds_a, ds_i) Y^{-1}(ds_a, ds_i) on the diagonal support (nds x nds,
 // column-major)
 __global__ void __launch_bounds__(256)
@@ -279,9 +323,9 @@ void launch_scm_cc(const DevStruct &d, const double *Xh, const double *Yi, doubl
         hipLaunchKernelGGL(k_gemm_nn, dim3((n + 63) / 64, (m * nc + 63) / 64, 2), dim3(256), 0, st, n, m * nc, n, Xh,
                            Yi, int64_t(n), d.ucat, int64_t(n), w.P, w.Pp, int64_t(n));
         hipLaunchKernelGGL(k_zero, dim3(grid_for(2 * blk * (m + 1), 256)), dim3(256), 0, st, 2 * blk * (m + 1), w.Q);
-        hipLaunchKernelGGL(k_cc_q, dim3(grid_for(d.nseg, 4)), dim3(256), 0, st, d.nseg, n, nc, d.seg_q, d.seg_row,
-                           d.seg_ptr, d.seg_col, d.seg_val, (const int *)nullptr, (const double *)nullptr, 0, w.YC,
-                           w.XC, w.Q, w.Qp);
+        hipLaunchKernelGGL(nc <= 16 ? k_cc_q16 : k_cc_q, dim3(grid_for(d.nseg, 4)), dim3(256), 0, st, d.nseg, n, nc,
+                           d.seg_q, d.seg_row, d.seg_ptr, d.seg_col, d.seg_val, (const int *)nullptr,
+                           (const double *)nullptr, 0, w.YC, w.XC, w.Q, w.Qp);
     }
     if (nds > 0) {
         // diagT(., q) = (X^ o Y^{-1})(Ds, Ds) D_q, then the U_q terms
@@ -308,9 +352,9 @@ void launch_scm_cc_extra_column(const DevStruct &d, const double *Mvec, const do
         hipLaunchKernelGGL(k_zero, dim3(grid_for(blk, 256)), dim3(256), 0, st, blk, w.Q + blk * m);
         hipLaunchKernelGGL(k_zero, dim3(grid_for(blk, 256)), dim3(256), 0, st, blk, w.Qp + blk * m);
         // rows of G: by symmetry, column j of the aggregate pattern lists the entries of row j
-        hipLaunchKernelGGL(k_cc_q, dim3(grid_for(n, 4)), dim3(256), 0, st, int64_t(n), n, nc, (const int *)nullptr,
-                           (const int *)nullptr, d.ag_cptr, d.ag_row, (const double *)nullptr, d.ag_slot, Mvec, m, w.YC, w.XC,
-                           w.Q, w.Qp);
+        hipLaunchKernelGGL(nc <= 16 ? k_cc_q16 : k_cc_q, dim3(grid_for(n, 4)), dim3(256), 0, st, int64_t(n), n, nc,
+                           (const int *)nullptr, (const int *)nullptr, d.ag_cptr, d.ag_row, (const double *)nullptr,
+                           d.ag_slot, Mvec, m, w.YC, w.XC, w.Q, w.Qp);
     }
     if (nds > 0) {
         launch_zcol(d, Xh, Mvec, Z, st);

@@ -69,13 +69,29 @@ __device__ double block_max(double v, double *sh) {
 // combines them in a fixed order.
 constexpr int kMetricsGroups = 64;
 
+// resid[k] = b_k - A_k . X for k < m: one wave per constraint, the entries split over
+// the lanes and summed in a fixed order (a constraint can hold many entries)
+__global__ void __launch_bounds__(256) k_con_resid(int m, const int64_t *__restrict__ con_ptr,
+                                                 const int *__restrict__ con_slot, const double *__restrict__ con_val,
+                                                 const double *__restrict__ b, const double *__restrict__ X,
+                                                 double *__restrict__ resid) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); k < m; k += waves) {
+        double a = 0.0;
+        for (int64_t e = con_ptr[k + 1] + lane; e < con_ptr[k + 2]; e += 64) a = fma(con_val[e], X[con_slot[e]], a);
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+        if (lane == 0) resid[k] = b[k] - a;
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const int64_t *__restrict__ con_ptr,
                                                   const int *__restrict__ con_slot,
                                                   const double *__restrict__ con_val,
                                                   const double *__restrict__ b, const double *__restrict__ wE,
                                                   const double *__restrict__ X, const double *__restrict__ Y,
                                                   const double *__restrict__ z, const double *__restrict__ G,
-                                                  double *__restrict__ part) {
+                                                  const double *__restrict__ resid, double *__restrict__ part) {
     __shared__ double sh[1024];
     const int t = threadIdx.x;
     const int64_t i0 = int64_t(blockIdx.x) * blockDim.x + t, step = int64_t(gridDim.x) * blockDim.x;
@@ -84,10 +100,7 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
     // A_0 . X over all threads (A_0 carries the whole aggregate pattern)
     for (int64_t e = con_ptr[0] + i0; e < con_ptr[1]; e += step) pobj += con_val[e] * X[con_slot[e]];
     for (int64_t k = 1 + i0; k <= m; k += step) {
-        double a = 0.0;
-        for (int64_t e = con_ptr[k]; e < con_ptr[k + 1]; ++e) a += con_val[e] * X[con_slot[e]];
-        const double r = b[k - 1] - a;
-        rmax = fmax(rmax, fabs(r));
+        rmax = fmax(rmax, fabs(resid[k - 1]));
         bz += b[k - 1] * z[k - 1];
         bad |= !isfinite(z[k - 1]);
     }
@@ -193,14 +206,18 @@ void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, 
                        d.asm_k, d.asm_val, y, a0, c1, in1, out);
 }
 
-size_t metrics_work_doubles() { return size_t(8) * kMetricsGroups; }
+size_t metrics_work_doubles(int m) { return size_t(8) * kMetricsGroups + size_t(m > 0 ? m : 1); }
 
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z, double *G,
                     double *scal, double *work, hipStream_t st) {
     // G = A_0 - sum z_k A_k - Y
     launch_assemble(d, z, 1.0, -1.0, Y, G, st);
+    double *resid = work + 8 * kMetricsGroups;
+    if (d.m > 0)
+        hipLaunchKernelGGL(k_con_resid, dim3((d.m + 3) / 4 < 4096 ? (d.m + 3) / 4 : 4096), dim3(256), 0, st, d.m,
+                           d.con_ptr, d.con_slot, d.con_val, d.b, X, resid);
     hipLaunchKernelGGL(k_metrics, dim3(kMetricsGroups), dim3(1024), 0, st, d.m, d.nslot, d.con_ptr, d.con_slot,
-                       d.con_val, d.b, d.wE, X, Y, z, G, work);
+                       d.con_val, d.b, d.wE, X, Y, z, G, (const double *)resid, work);
     hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(64), 0, st, kMetricsGroups, (const double *)work, scal);
 }
 

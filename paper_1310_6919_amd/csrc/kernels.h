@@ -140,7 +140,7 @@ constexpr int kZmRows = 128;
 // out[s] = sum_t asm_val[t] * coef_k  + c1 * in1[s]; coef_0 = a0, coef_k = -y[k-1]
 void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, const double *in1,
                      double *out, hipStream_t st);
-size_t metrics_work_doubles();   // work of launch_metrics
+size_t metrics_work_doubles(int m);   // work of launch_metrics
 // scal[...] <- pobj, dobj, max|r|, max|G|, X.Y, also G_E (see k_vec.hip)
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z,
                     double *G, double *scal, double *work, hipStream_t st);
