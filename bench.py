@@ -284,6 +284,57 @@ def standalone_scm(h, prob, reps=5):
     return sum(med) * 1e-3, phases
 
 
+def batch_solve(args):
+    """The same 256 instances through the batched solver (sdpc_batch_solve): host
+    workers with one HIP stream each keep many instances in flight; the block width
+    is tuned per size class.  One step is the whole batch (analysis, tuning, creates,
+    solves and releases)."""
+    import numpy as np
+    import torch
+    import sdpgen
+    from paper_1310_6919_amd.sdpc import sdpc_batch_solve
+    probs = sdpgen.maxcut_ktree_batch(256, 0)
+    prm = [{"user_perm": np.arange(p.n)[::-1].astype(np.int32)} for p in probs]
+    times, opts, iters = [], [], []
+    for step in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _, opt = sdpc_batch_solve(probs, prm, workers=args.batch_workers, autotune=True, want_z=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if step >= args.warmup:
+            times.append(dt)
+            opts.append(opt)
+            iters.extend(r["iters"] for r in res)
+        log(f"batch pass {step}: {dt:.2f} s (tune {opt['tune_ms']:.0f} ms, create {opt['create_ms']:.0f} ms, "
+            f"solve {opt['solve_ms']:.0f} ms), widths {opt['tuned_width']}")
+    elapsed = sum(times)
+    out = {
+        "metric": "batched solves of the 256-instance k-tree max-cut batch, gap 1e-7",
+        "value": len(probs) * args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "256 max-cut SDPs, n~U[50,800], random k-trees k~U[3,12], 30% edges dropped, "
+                               "w~U[0,1], seed 0, reverse insertion order; batched", "gap_tol": 1e-7,
+                   "workers": args.batch_workers,
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "runtime default")},
+        "phases_ms": {k: statistics.median(o[k] for o in opts) for k in ("tune_ms", "create_ms", "solve_ms",
+                                                                          "total_ms")},
+        "tuned_width": opts[-1]["tuned_width"],
+        "iters_mean": float(np.mean(iters)),
+        "iters_max": int(max(iters)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def batch_loop(args):
     """256 independent max-cut SDPs (n uniform in [50, 800], random k-trees with k in
     [3, 12] and 30% of the edges dropped, weights U[0,1], seed 0), each created and
@@ -348,8 +399,13 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy / FP64 GEMM peak measurement")
     ap.add_argument("--workload", default="band4000",
                     help="band4000 (the metric's workload), normmin (norm minimisation, n = 2010, m = 64), "
-                         "cfg1 (max-cut, n = m = 64), latticeP (P x 10 lattice max-cut, e.g. lattice400) "
-                         "or ktree256 (256 uneven k-tree max-cut SDPs, one plain solve each)")
+                         "cfg1 (max-cut, n = m = 64), latticeP (P x 10 lattice max-cut, e.g. lattice400), "
+                         "ktree256 (256 uneven k-tree max-cut SDPs through the batched solver) or "
+                         "ktree256plain (the same, one plain solve after another)")
+    ap.add_argument("--batch-workers", type=int, default=16, help="host workers of the batched solver")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues of the HIP runtime (GPU_MAX_HW_QUEUES, set before the runtime "
+                         "starts; 0 keeps the runtime's default)")
     ap.add_argument("--factorization", type=int, default=0, choices=(0, 1),
                     help="0: X^ through Algorithm 1's Lhat (the method); 1: the earlier X^ = L^T D L "
                          "(the factorisation ablation)")
@@ -365,6 +421,10 @@ def main():
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "ktree256" and args.hw_queues == 0:
+        args.hw_queues = 16   # one hardware queue per batch worker
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))   # read when the runtime starts (at most 32)
     import torch
     from paper_1310_6919_amd import sdpc_create
     if not torch.cuda.is_available():
@@ -380,6 +440,9 @@ def main():
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     if args.workload == "ktree256":
+        batch_solve(args)
+        return
+    if args.workload == "ktree256plain":
         batch_loop(args)
         return
     prob, cparams, desc = workload(args.workload)

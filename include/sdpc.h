@@ -104,6 +104,12 @@ typedef struct {
                                   block do not grow (explicit zeros only: E and every
                                   result are unchanged, the block walks get shorter);
                                   0 merges chains only                             (1)      */
+    int32_t dual_points;       /* dual step length (Step 3): test points per round of the
+                                  parallel positive-definiteness search; 0 takes 511 points
+                                  then 384 (two rounds, made for one instance alone on the
+                                  GPU); otherwise rounds of this many points (2..511) until
+                                  the bracket is narrower than 5e-5 relative       (0)      */
+    int32_t pad_;              /* 0                                                        */
     const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
                                   i-th (host, read at create)                              */
 } sdpc_params;
@@ -272,6 +278,42 @@ sdpc_status sdpc_get_direction(const sdpc_handle *h, double *d_dz, double *d_dX_
  * [Y factor, Algorithm 1, solves, SCM assembly, SCM Cholesky].  Host array
  * of 5.  Synchronises. */
 sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5);
+
+/* Batched solves: many independent SDPs of uneven sizes on one GPU, each solved
+ * as by sdpc_solve (Section 2.2, Steps 0-4 with the Schur complement phase of
+ * Section 3.1) while many are in flight at once.  The independent Schur
+ * complement columns of the paper's parallel scheme (Section 3.2) become
+ * independent instances here: host workers, one HIP stream each, take the
+ * instances longest estimated work first; every handle is created before any
+ * solve starts and released after all have finished; an instance retires as
+ * soon as its own stopping test holds.  With autotune the storage-block width
+ * (the tile width of the clique panels) is chosen per size class (largest
+ * clique <= 8 / <= 16 / more, times n <= 200 / <= 500 / more) by timing real
+ * iterations of the class's largest instance at widths 8, 16 and 32. */
+typedef struct {
+    int32_t workers;           /* host workers, one HIP stream each, 1..64           (8)  */
+    int32_t autotune;          /* 1: choose the block width per size class            (1)  */
+    int32_t tuned_width[9];    /* out: width chosen per class (3 x clique class + order
+                                  class), 0 where no instance fell in the class          */
+    int32_t dual_points;       /* dual_points of every instance whose params leave it 0:
+                                  many instances share the GPU, so each searches the dual
+                                  step with fewer points per round                    (32) */
+    double tune_ms, create_ms, solve_ms, total_ms;   /* out: wall time of the phases        */
+} sdpc_batch_options;
+
+/* Defaults listed above. */
+sdpc_batch_options sdpc_default_batch_options(void);
+
+/* probs (host, count), params (host, count, may be NULL for defaults; each
+ * instance's own user_perm is honoured), opt (host, may be NULL; receives the
+ * tuning outcome and times), results (host, count): each instance's outcome as
+ * from sdpc_solve (results[i].status its status).  d_z (host array of count
+ * device pointers, may be NULL, entries may be NULL): z of each instance
+ * (length m_i).  The device is the current one.  Returns SDPC_OK when every
+ * instance solved, else the status of the first one that did not (the others
+ * are still solved); the detail is in sdpc_last_error(NULL).  Synchronises. */
+sdpc_status sdpc_batch_solve(int32_t count, const sdpc_problem *probs, const sdpc_params *params,
+                             sdpc_batch_options *opt, sdpc_result *results, double *const *d_z);
 
 /* Centring: Newton steps of Step 2 of Section 2.2 from the handle's current
  * iterate with the centring target beta mu replaced by the fixed mu (> 0), so

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUTDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUTDIR, "libsdpc.so")
-SOURCES = ["symbolic.cpp", "api.cpp", "k_vec.hip", "k_factor.hip", "k_solve.hip", "k_scm.hip", "k_scm_cc.hip", "k_dense.hip", "potrf_static.hip"]
+SOURCES = ["symbolic.cpp", "api.cpp", "k_vec.hip", "k_factor.hip", "k_solve.hip", "k_scm.hip", "k_scm_cc.hip", "k_dense.hip", "potrf_static.hip", "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SDPC_OFFLOAD_ARCH", "gfx950")

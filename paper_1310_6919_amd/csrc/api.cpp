@@ -39,6 +39,7 @@ namespace {
 // points inside the bracket (relative spacing ~9.6e-5) and their 384 gamma twins.
 constexpr int kDualRounds = 2;
 constexpr int kDualTest[kDualRounds] = {511, 384};
+constexpr int kMaxDualRounds = 16;
 constexpr int kCand = 1024;      // the most candidates of a round
 constexpr int kMaxClique = 64;   // largest clique of the clique kernels (register tiles of 64 x 64)
 constexpr int kMaxPanel = 4096;  // largest storage panel (doubles): 32 KiB of LDS
@@ -94,6 +95,8 @@ struct sdpc_handle {
     bool metrics_ready = false; // msc holds the metrics of the current iterate (read with the last step)
     double msc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int iters = 0;
+    int dual_rounds = 0;            // schedule of the dual step's rounds
+    int dual_test[16] = {0};
 };
 
 namespace sdpc {
@@ -177,6 +180,8 @@ sdpc_params sdpc_default_params(void) {
     p.solve_kernel = 0;
     p.factorization = 0;
     p.merge_siblings = 1;
+    p.dual_points = 0;
+    p.pad_ = 0;
     p.user_perm = nullptr;
     return p;
 }
@@ -222,6 +227,8 @@ static sdpc_status check_problem(const sdpc_problem *prob, sdpc_handle *h) {
     if (h->prm.solve_kernel < 0 || h->prm.solve_kernel > 1) return fail(h, SDPC_E_ARG, "solve_kernel must be 0 or 1");
     if (h->prm.factorization < 0 || h->prm.factorization > 1)
         return fail(h, SDPC_E_ARG, "factorization must be 0 or 1");
+    if (h->prm.dual_points != 0 && (h->prm.dual_points < 2 || h->prm.dual_points > 511))
+        return fail(h, SDPC_E_ARG, "dual_points must be 0 or 2..511");
     const int64_t nnz = prob->ptr[m + 1];
     if (prob->ptr[0] != 0 || nnz < 0) return fail(h, SDPC_E_ARG, "ptr must start at 0");
     for (int k = 0; k <= m; ++k)
@@ -298,6 +305,22 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     h->m = m;
     h->prm = params ? *params : sdpc_default_params();
     TRY(check_problem(prob, h));
+    // dual-step schedule: round 0 a log grid of P points over [1e-8, 1], every later
+    // round P even points inside the bracket, until the bracket is narrower than 5e-5
+    // of its lower end
+    if (h->prm.dual_points == 0) {
+        h->dual_rounds = kDualRounds;
+        for (int r = 0; r < kDualRounds; ++r) h->dual_test[r] = kDualTest[r];
+    } else {
+        const int P = h->prm.dual_points;
+        double width = std::pow(10.0, 8.0 / (P - 1)) - 1.0;
+        h->dual_rounds = 1;
+        h->dual_test[0] = P;
+        while (width > 5e-5 && h->dual_rounds < kMaxDualRounds) {
+            h->dual_test[h->dual_rounds++] = P;
+            width /= (P + 1);
+        }
+    }
     std::vector<int> arow, acol;
     TRY(analyze_impl(prob, h, arow, acol));
     const Symbolic &S = h->S;
@@ -965,7 +988,7 @@ double since(std::chrono::steady_clock::time_point t0) {
 sdpc_status dual_step_launch(sdpc_handle *h) {
     HIPCHK(h, hipEventRecord(h->ev_dy, h->st));
     HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_dy, 0));
-    launch_dual_step(h->d, h->Y, h->dY, kDualRounds, kDualTest, h->prm.gamma, h->cand, h->ubuf, h->ydw_dual,
+    launch_dual_step(h->d, h->Y, h->dY, h->dual_rounds, h->dual_test, h->prm.gamma, h->cand, h->ubuf, h->ydw_dual,
                      h->flags, h->alphas, h->side);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipEventRecord(h->ev_dual, h->side));

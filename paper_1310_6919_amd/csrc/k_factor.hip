@@ -596,8 +596,8 @@ k_alpha_cl_wave(int ncl, const int64_t *__restrict__ cl_ptr, const int64_t *__re
 // keep the longest prefix of successful test points and narrow
 // bracket = (lo, hi, settled, twin): twin is the candidate index holding the
 // factor of Y + gamma lo dY, or -1 if that factor was not formed.
-__global__ void __launch_bounds__(1024) k_bracket(int ntest, int round, double gamma, const int *__restrict__ fail,
-                                                   double *__restrict__ bracket) {
+__global__ void __launch_bounds__(1024) k_bracket(int ntest, int round, int twins, double gamma,
+                                                   const int *__restrict__ fail, double *__restrict__ bracket) {
     __shared__ int first;   // first test point that failed (ntest if none)
     if (round > 0 && bracket[2] != 0.0) return;   // uniform: settled
     if (threadIdx.x == 0) first = ntest;
@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(1024) k_bracket(int ntest, int round, double g
     }
     const double lo = best >= 0 ? cand(best) : bracket[0];
     const double hi = best + 1 < ntest ? cand(best + 1) : bracket[1];
-    const double twin = (best >= 0 && fail[ntest + best] == 0) ? double(ntest + best) : -1.0;
+    const double twin = (twins && best >= 0 && fail[ntest + best] == 0) ? double(ntest + best) : -1.0;
     bracket[0] = lo;
     bracket[1] = hi;
     bracket[3] = twin;
@@ -684,7 +684,11 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, d
                        (const double *)nullptr, 0, 1, 0.0, L, int64_t(0), fail);
 }
 
-int dual_step_candidates(int round, const int *ntest) { return round == 0 ? ntest[0] + 1 : 2 * ntest[round]; }
+// round 0: its test points and the twin of alpha = 1; later rounds: their test points,
+// and in the last round one twin per test point (the twin of the step finally taken)
+int dual_step_candidates(int round, int rounds, const int *ntest) {
+    return round == 0 ? ntest[0] + 1 : (round == rounds - 1 ? 2 * ntest[round] : ntest[round]);
+}
 
 void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int rounds, const int *ntest,
                       double gamma, double *cand, double *U, double *work, int *fail, double *bracket,
@@ -694,7 +698,7 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
     if (d.max_h <= 64)
         hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, Y, dY, yd);
     for (int r = 0; r < rounds; ++r) {
-        const int nc = dual_step_candidates(r, ntest);
+        const int nc = dual_step_candidates(r, rounds, ntest);
         if (d.max_h <= 64) {
             launch_wave_chol(d, nc, yd, true, bracket, r, ntest[r], gamma, cand, d.nslot, U, fail, st);
         } else {
@@ -702,7 +706,8 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
                                d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_slot, Y, dY, (const double *)bracket,
                                r, ntest[r], gamma, cand, d.nslot, fail);
         }
-        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(1024), 0, st, ntest[r], r, gamma, (const int *)fail, bracket);
+        hipLaunchKernelGGL(k_bracket, dim3(1), dim3(1024), 0, st, ntest[r], r, (r > 0 && r == rounds - 1) ? 1 : 0,
+                           gamma, (const int *)fail, bracket);
     }
 }
 

@@ -168,7 +168,7 @@ size_t wave_chol_work_doubles(const DevStruct &d);
 size_t wave_chol_lds_bytes(int max_h, int64_t npool);
 // largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of
 // parallel factorisations of ntest[r] test points (log grid, then even grids inside
-// the bracket) plus their gamma twins; the result is bracket[0] (a lower bound;
+// the bracket), with gamma twins in the last round; the result is bracket[0] (a lower bound;
 // bracket[1] an upper bound), bracket[3] the candidate holding the factor of
 // Y + gamma bracket[0] dY (or -1), all on the device.  Only the gamma twins store
 // their factors (in cand, d.nslot doubles each); the other tests keep nothing.
@@ -176,7 +176,7 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
                       double gamma, double *cand, double *U, double *work, int *fail, double *bracket,
                       hipStream_t st);
 // candidates launched in a round (test points and their gamma twins)
-int dual_step_candidates(int round, const int *ntest);
+int dual_step_candidates(int round, int rounds, const int *ntest);
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,

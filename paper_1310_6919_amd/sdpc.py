@@ -22,7 +22,7 @@ SDPC_OK, SDPC_E_ARG, SDPC_E_PATTERN, SDPC_E_NOT_PD, SDPC_E_HIP, SDPC_E_MAXITER, 
 EXPORTS = ["sdpc_default_params", "sdpc_analyze", "sdpc_create", "sdpc_solve", "sdpc_reset", "sdpc_step", "sdpc_scm",
            "sdpc_potrf", "sdpc_get_pattern", "sdpc_get_cliques", "sdpc_get_solution", "sdpc_set_state",
            "sdpc_get_factors", "sdpc_get_dense", "sdpc_complete_dense", "sdpc_get_direction", "sdpc_get_scm_timing",
-           "sdpc_center", "sdpc_adjoint", "sdpc_potrf_static", "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
+           "sdpc_default_batch_options", "sdpc_batch_solve", "sdpc_center", "sdpc_adjoint", "sdpc_potrf_static", "sdpc_status_string", "sdpc_last_error", "sdpc_destroy"]
 
 
 class sdpc_problem(C.Structure):
@@ -36,7 +36,8 @@ class sdpc_params(C.Structure):
                 ("beta_infeas", C.c_double), ("gamma", C.c_double), ("lambda0", C.c_double),
                 ("max_iter", C.c_int32), ("ordering", C.c_int32), ("block_width", C.c_int32),
                 ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("solve_kernel", C.c_int32),
-                ("factorization", C.c_int32), ("merge_siblings", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+                ("factorization", C.c_int32), ("merge_siblings", C.c_int32), ("dual_points", C.c_int32),
+                ("pad_", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
 
 
 class sdpc_analysis(C.Structure):
@@ -48,6 +49,17 @@ class sdpc_analysis(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class sdpc_batch_options(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("autotune", C.c_int32), ("tuned_width", C.c_int32 * 9),
+                ("dual_points", C.c_int32), ("tune_ms", C.c_double), ("create_ms", C.c_double),
+                ("solve_ms", C.c_double), ("total_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["tuned_width"] = list(self.tuned_width)
+        return d
 
 
 class sdpc_result(C.Structure):
@@ -92,6 +104,8 @@ def load():
         "sdpc_complete_dense": (I32, [VP, VP]),
         "sdpc_get_direction": (I32, [VP, VP, VP, VP, P(D)]),
         "sdpc_get_scm_timing": (I32, [VP, P(D)]),
+        "sdpc_default_batch_options": (sdpc_batch_options, []),
+        "sdpc_batch_solve": (I32, [I32, VP, VP, P(sdpc_batch_options), VP, VP]),
         "sdpc_center": (I32, [VP, D, I32, D, P(I32), P(D)]),
         "sdpc_adjoint": (I32, [VP, VP, VP, VP, VP]),
         "sdpc_potrf_static": (I32, [VP, I64, I32, VP, VP]),
@@ -344,6 +358,39 @@ def sdpc_potrf_static(B, m=None, info=None, stream=None):
     if st != SDPC_OK:
         raise SdpcError(st, "sdpc_potrf_static: " + lib.sdpc_last_error(None).decode())
     return B
+
+
+def sdpc_batch_solve(probs, params=None, workers=8, autotune=True, want_z=True, dual_points=None):
+    """Solve many SDPs at once (sdpc_batch_solve).  params: None, one dict for all,
+    or a list of dicts (e.g. per-instance user_perm).  Returns (results, z list,
+    options dict); raises SdpcError if an instance fails."""
+    import torch
+    lib = load()
+    count = len(probs)
+    keep = []
+    probs_arr = (sdpc_problem * max(count, 1))()
+    prm_arr = (sdpc_params * max(count, 1))()
+    for i, p in enumerate(probs):
+        probs_arr[i] = _problem_struct(p, keep)
+        pd = params[i] if isinstance(params, (list, tuple)) else (params or {})
+        prm_arr[i] = _params_struct(pd, keep)
+    opt = lib.sdpc_default_batch_options()
+    opt.workers = int(workers)
+    opt.autotune = int(bool(autotune))
+    if dual_points is not None:
+        opt.dual_points = int(dual_points)
+    res = (sdpc_result * max(count, 1))()
+    zs = [torch.empty(int(p.m), dtype=torch.float64, device="cuda") for p in probs] if want_z else None
+    zp = (C.c_void_p * max(count, 1))(*([z.data_ptr() for z in zs] if zs else [None] * count)) if want_z else None
+    torch.cuda.synchronize()
+    st = lib.sdpc_batch_solve(count, probs_arr, prm_arr, C.byref(opt), res, zp)
+    out = []
+    for i in range(count):
+        d = res[i].as_dict()
+        out.append(d)
+    if st != SDPC_OK:
+        raise SdpcError(st, "sdpc_batch_solve: " + lib.sdpc_last_error(None).decode())
+    return out, zs, opt.as_dict()
 
 
 def sdpc_create(prob, stream=None, **params) -> Handle:
