@@ -409,6 +409,9 @@ def main():
     ap.add_argument("--factorization", type=int, default=0, choices=(0, 1),
                     help="0: X^ through Algorithm 1's Lhat (the method); 1: the earlier X^ = L^T D L "
                          "(the factorisation ablation)")
+    ap.add_argument("--chol-kernel", type=int, default=0, choices=(0, 1),
+                    help="SCM Cholesky: 0 one dataflow launch per factorisation, 1 one launch per "
+                         "64-column block")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "potrf_traffic.json"),
                     help="HBM traffic per factorisation from rocprofv3 counters (json), if present")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -448,6 +451,8 @@ def main():
     prob, cparams, desc = workload(args.workload)
     if args.factorization:
         cparams = dict(cparams, factorization=args.factorization)
+    if args.chol_kernel:
+        cparams = dict(cparams, chol_kernel=args.chol_kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = sdpc_create(prob, **cparams)
@@ -475,7 +480,8 @@ def main():
     scm_alone, phases = standalone_scm(h, prob)
     potrf_ms = sum(r["t_potrf_ms"] for r in results) / max(1, sum(r["n_potrf"] for r in results))
     m = prob.m
-    launches = (m + 63) // 64
+    flow = int(h.params.chol_kernel) == 0
+    launches = 1 if flow else (m + 63) // 64
     flops = m ** 3 / 3.0
     achieved = flops / (potrf_ms * 1e-3) / 1e12
     traffic = None
@@ -483,7 +489,8 @@ def main():
         # counters count only for the kernel source they were taken on
         try:
             rec = json.load(open(args.traffic))
-            if rec.get("source_sha1") == source_sha1(KERNEL_SOURCE) and rec.get("m", 4000) == m:
+            if (rec.get("source_sha1") == source_sha1(KERNEL_SOURCE) and rec.get("m", 4000) == m
+                    and rec.get("kernel") == ("k_chol_flow" if flow else "k_chol_step")):
                 traffic = rec.get("bytes_per_factorisation")
         except Exception:
             traffic = None
@@ -501,7 +508,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": prob.n, "m": m, "gap_tol": 1e-7,
-                   "block_width": int(h.params.block_width), "factorization": int(h.params.factorization)},
+                   "block_width": int(h.params.block_width), "factorization": int(h.params.factorization),
+                   "chol_kernel": int(h.params.chol_kernel)},
         "scm_s_per_iter": scm_alone,
         "scm_s_per_iter_in_solve": scm_in_solve,
         "phase_roofline": phases,
@@ -514,8 +522,9 @@ def main():
             "pmatrix_and_steps": statistics.median([r["t_pmatrix_ms"] / r["iters"] for r in results]),
         },
         "roofline": {
-            "kernel": "SCM Cholesky: k_chol_step, one launch per 64-column block (%d per factorisation); "
-                      "per-launch figures are averages over the launches of a factorisation" % launches,
+            "kernel": ("SCM Cholesky: k_chol_flow, one dataflow launch per factorisation" if flow else
+                       "SCM Cholesky: k_chol_step, one launch per 64-column block (%d per factorisation); "
+                       "per-launch figures are averages over the launches of a factorisation" % launches),
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,

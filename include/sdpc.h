@@ -109,7 +109,11 @@ typedef struct {
                                   then 384 (two rounds, made for one instance alone on the
                                   GPU); otherwise rounds of this many points (2..511) until
                                   the bracket is narrower than 5e-5 relative       (0)      */
-    int32_t pad_;              /* 0                                                        */
+    int32_t chol_kernel;       /* SCM Cholesky (type (i) of Section 3.1): 0 one launch, a
+                                  dataflow over the 64-column blocks (tiles updated
+                                  left-looking, each block's tiles finished together);
+                                  1 one launch per 64-column block; both give the same
+                                  factor up to rounding order                      (0)      */
     const int32_t *user_perm;  /* ordering == 2: user_perm[i] = original index eliminated
                                   i-th (host, read at create)                              */
 } sdpc_params;

@@ -88,7 +88,10 @@ struct sdpc_handle {
     hipStream_t side = nullptr;   // second stream (default priority): dual step alongside dX and alpha_p
     hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
     int *pflags_b = nullptr;   // hand-over flags of the SCE backward solve
+    int *pflags_f = nullptr;   // tile flags of the one-launch SCM Cholesky
+    int epoch_f = 0;           // last epoch used on those flags
     double *pwork = nullptr;   // diagonal factors of the SCM Cholesky waiting for the next launch
+    double *pwork_f = nullptr; // diagonal blocks parked by the one-launch SCM Cholesky
     int epoch = 0;                                    // last epoch used on those flags
     int next_cand = -1;   // dual-step candidate holding the factor of the current Y, or -1
     bool xside_ready = false;   // Lhat and its diagonal inverses already belong to the current X
@@ -181,7 +184,7 @@ sdpc_params sdpc_default_params(void) {
     p.factorization = 0;
     p.merge_siblings = 1;
     p.dual_points = 0;
-    p.pad_ = 0;
+    p.chol_kernel = 0;
     p.user_perm = nullptr;
     return p;
 }
@@ -227,6 +230,7 @@ static sdpc_status check_problem(const sdpc_problem *prob, sdpc_handle *h) {
     if (h->prm.solve_kernel < 0 || h->prm.solve_kernel > 1) return fail(h, SDPC_E_ARG, "solve_kernel must be 0 or 1");
     if (h->prm.factorization < 0 || h->prm.factorization > 1)
         return fail(h, SDPC_E_ARG, "factorization must be 0 or 1");
+    if (h->prm.chol_kernel < 0 || h->prm.chol_kernel > 1) return fail(h, SDPC_E_ARG, "chol_kernel must be 0 or 1");
     if (h->prm.dual_points != 0 && (h->prm.dual_points < 2 || h->prm.dual_points > 511))
         return fail(h, SDPC_E_ARG, "dual_points must be 0 or 2..511");
     const int64_t nnz = prob->ptr[m + 1];
@@ -776,7 +780,9 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->T, std::max<size_t>(size_t(d.nS), 1)));
     TRY(dalloc(h, &h->B, size_t(h->ldb) * std::max(m, 1)));
     TRY(dalloc(h, &h->pflags_b, size_t(potrf_flag_count(m))));
+    TRY(dalloc(h, &h->pflags_f, size_t(potrf_flow_flag_count(m, m + 1))));
     TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
+    TRY(dalloc(h, &h->pwork_f, potrf_flow_work_doubles(m)));
     TRY(dalloc(h, &h->scal, 16));
     TRY(dalloc(h, &h->mwork, metrics_work_doubles(m)));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
@@ -792,6 +798,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flow_flag_count(m, m + 1) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
     for (auto &e : h->evs) HIPCHK(h, hipEventCreate(&e));
     HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
@@ -925,6 +932,15 @@ void read_scm_timing(sdpc_handle *h) {
     }
 }
 
+// SCM Cholesky of the leading m columns of B with rows m .. rows - 1 riding along,
+// in the form the parameters choose; fail: pivot + 1, or -1 if a hand-over wait ran out.
+void potrf_rows(sdpc_handle *h, int m, int rows, double *B, int64_t ldb, int *fail) {
+    if (h->prm.chol_kernel == 0)
+        launch_potrf_flow(m, rows, B, ldb, h->pflags_f, h->pwork_f, ++h->epoch_f, fail, h->st);
+    else
+        launch_potrf_rows(m, rows, B, ldb, h->pwork, fail, h->st);
+}
+
 // The factor X^ is applied through, from Xbar: Lhat of Algorithm 1 (X^{-1} = Lhat
 // Lhat^T), or with factorization 1 the unit-lower L^{-1} and the block diagonal D of
 // X^ = L^T D L (eq. sparse_fact); then the inverses of the factor's diagonal blocks.
@@ -969,7 +985,7 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
     HIPCHK(h, hipEventRecord(h->evs[4], st));
-    if (factor) launch_potrf(d.m, B, ldb, h->pwork, h->flags + kCand + 2, st);
+    if (factor) potrf_rows(h, d.m, d.m, B, ldb, h->flags + kCand + 2);
     HIPCHK(h, hipEventRecord(h->evs[5], st));
     HIPCHK(h, hipGetLastError());
     if (in_step) return SDPC_OK;
@@ -1069,7 +1085,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     HIPCHK(h, hipEventRecord(ev[1], st));
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
     launch_set_row(d.m, h->g, h->B + d.m, h->ldb, st);
-    launch_potrf_rows(d.m, d.m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    potrf_rows(h, d.m, d.m + 1, h->B, h->ldb, h->flags + kCand + 2);
     HIPCHK(h, hipEventRecord(ev[6], st));
     launch_potrs_bwd(d.m, h->B, h->ldb, h->B + d.m, h->ldb, h->dz, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
     HIPCHK(h, hipEventRecord(ev[2], st));
@@ -1207,7 +1223,7 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m) {
     if (!h || !d_B || m < 0 || ldb < m || m > h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_potrf arguments") : SDPC_E_ARG;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), h->st));
-    launch_potrf(m, d_B, ldb, h->pwork, h->flags + kCand + 2, h->st);
+    potrf_rows(h, m, m, d_B, ldb, h->flags + kCand + 2);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(h->st));
     const int f = read_flag(h, kCand + 2);
@@ -1381,7 +1397,7 @@ sdpc_status sdpc_adjoint(sdpc_handle *h, const double *d_GL_E, const double *d_d
     launch_add(m, h->hcol, d_dLdz, h->g, st);
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
     launch_set_row(m, h->g, h->B + m, h->ldb, st);
-    launch_potrf_rows(m, m + 1, h->B, h->ldb, h->pwork, h->flags + kCand + 2, st);
+    potrf_rows(h, m, m + 1, h->B, h->ldb, h->flags + kCand + 2);
     launch_potrs_bwd(m, h->B, h->ldb, h->B + m, h->ldb, d_gb, h->pflags_b, ++h->epoch, h->flags + kCand + 2, st);
     // dL/dA_0 = sym(X^ (sum_k lambda_k A_k - G_L) Y^{-1}) on E: the dX kernels with
     // M = G_L - sum_k lambda_k A_k, no beta mu term and a zero Xbar give -sym(X^ M Y^{-1})

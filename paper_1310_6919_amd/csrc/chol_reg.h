@@ -1,6 +1,6 @@
 // Small dense Cholesky factorisations kept in registers.
 //
-// One row per lane, one wave (lane_bcast, elim_step_bcast, elim32_lds): the
+// One row per lane, one wave (lane_bcast, elim_step_bcast, elim_lds): the
 // one-wave sparse factorisations (Y = N N^T and the dual step's candidates, the
 // clique-wise step-length test) and the diagonal blocks of the dense SCM Cholesky.
 //
@@ -65,7 +65,7 @@ __device__ inline void elim_step_bcast(double (&a)[32], double l, int k, int c0)
     }
 }
 
-// Right-looking elimination of 32 columns held one row per lane, a[k] = A(lane,
+// Right-looking elimination of W columns held one row per lane, a[k] = A(lane,
 // c0 + k), pivot k in lane c0 + k; lanes above the pivot get zero multipliers and
 // row c0 + k gets sqrt(d).  A pivot that is not positive and finite leaves a NaN
 // (or 0 * inf) on the diagonal.  The arithmetic and its order are those of one
@@ -77,25 +77,26 @@ __device__ inline void elim_step_bcast(double (&a)[32], double l, int k, int c0)
 // pivot's 1/sqrt is formed while the reads are in flight.  Fewer issue slots than
 // readlanes for every multiplier (a wave alone on its SIMD is issue-bound there),
 // at the cost of registers for the values in flight.
-__device__ inline void elim32_lds(double (&a)[32], int c0, double *Wl) {
+template <int W>
+__device__ inline void elim_lds(double (&a)[W], int c0, double *Wl) {
     const int lane = threadIdx.x % 64;
     double inv = rsqrt_newton(lane_bcast(a[0], c0));
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
+    for (int k = 0; k < W; ++k) {
         __builtin_amdgcn_sched_barrier(0);
         const double l = (lane >= c0 + k) ? a[k] * inv : 0.0;
         a[k] = l;
-        if (k + 1 < 32) {
+        if (k + 1 < W) {
             Wl[(lane - c0) & 63] = l;   // every lane: no branch
             a[k + 1] = fma(-l, lane_bcast(l, c0 + k + 1), a[k + 1]);
-            double lj[32];
+            double lj[W];
 #pragma unroll
-            for (int j = k + 2; j < 32; ++j) lj[j] = Wl[j];
+            for (int j = k + 2; j < W; ++j) lj[j] = Wl[j];
             __builtin_amdgcn_sched_barrier(0);
             inv = rsqrt_newton(lane_bcast(a[k + 1], c0 + k + 1));
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int j = k + 2; j < 32; ++j) a[j] = fma(-l, lj[j], a[j]);
+            for (int j = k + 2; j < W; ++j) a[j] = fma(-l, lj[j], a[j]);
         }
     }
     __builtin_amdgcn_sched_barrier(0);

@@ -253,6 +253,14 @@ int potrf_flag_count(int m);
 size_t potrf_work_doubles(int m);
 void launch_potrf(int m, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
 void launch_potrf_rows(int m, int rows, double *B, int64_t ldb, double *work, int *fail, hipStream_t st);
+// The same factorisation in one launch (dataflow over the 64-column blocks, every
+// tile's left-looking updates kept in registers): flags hold
+// potrf_flow_flag_count(m, rows) ints, zeroed once; epoch must differ from every
+// earlier call's on the same flags; work: potrf_flow_work_doubles(m) doubles
+int potrf_flow_flag_count(int m, int rows);
+size_t potrf_flow_work_doubles(int m);
+void launch_potrf_flow(int m, int rows, double *B, int64_t ldb, int *flags, double *work, int epoch, int *fail,
+                       hipStream_t st);
 // R^T x = u with R the factor left in B and u read with stride ustride
 void launch_potrs_bwd(int m, const double *R, int64_t ldb, const double *u, int64_t ustride, double *x, int *flags,
                       int epoch, int *fail, hipStream_t st);

@@ -37,7 +37,7 @@ class sdpc_params(C.Structure):
                 ("max_iter", C.c_int32), ("ordering", C.c_int32), ("block_width", C.c_int32),
                 ("verbose", C.c_int32), ("pool_lds_bytes", C.c_int32), ("solve_kernel", C.c_int32),
                 ("factorization", C.c_int32), ("merge_siblings", C.c_int32), ("dual_points", C.c_int32),
-                ("pad_", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+                ("chol_kernel", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
 
 
 class sdpc_analysis(C.Structure):

@@ -45,13 +45,14 @@ CASES = {
 
 
 # ----------------------------------------------------------------- dense Cholesky
-# last blocks of every width class: one column, under / at / over half a block (the
-# second 32-column panel empty, exactly full, partly real), full
-@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 96, 97, 100, 128, 130, 200, 257])
-def test_potrf_matches_lapack(m):
+# last blocks of every width class: one column, at and just over each 16-column
+# panel boundary of a block (later panels empty, exactly full, partly real), full
+@pytest.mark.parametrize("m", [1, 5, 63, 64, 65, 80, 81, 96, 97, 100, 112, 113, 128, 130, 200, 257])
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_potrf_matches_lapack(m, kernel):
     rng = np.random.default_rng(m)
     prob = sdpgen.maxcut_band(300, 3, 1.0, 0)
-    h = _create(prob)
+    h = _create(prob, chol_kernel=kernel)
     A = sdpgen.random_pd_dense(m, rng, cond=1e3)
     Bt = dev(A.T.copy()).T            # column-major view
     upper_marker = np.triu(np.full((m, m), 7.0), 1)
@@ -64,12 +65,13 @@ def test_potrf_matches_lapack(m):
     h.close()
 
 
-# the failing pivot in either 32-column panel of a block, in the first block and a
+# the failing pivot in each 16-column panel of a block, in the first block and a
 # later one, and the last pivot of a ragged last block
-@pytest.mark.parametrize("m,piv", [(80, 50), (80, 3), (130, 70), (130, 127), (130, 129)])
-def test_potrf_reports_not_pd(m, piv):
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("m,piv", [(80, 3), (80, 20), (80, 40), (80, 50), (130, 70), (130, 127), (130, 129)])
+def test_potrf_reports_not_pd(m, piv, kernel):
     prob = sdpgen.maxcut_band(300, 3, 1.0, 0)   # handle sized for m <= 300
-    h = _create(prob)
+    h = _create(prob, chol_kernel=kernel)
     A = np.eye(m)
     A[piv, piv] = -1.0
     Bt = dev(A.T.copy()).T

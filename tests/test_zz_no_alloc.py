@@ -34,7 +34,8 @@ def _colmajor(A):
 def test_static_potrf_matches_handle_potrf_twice():
     from paper_1310_6919_amd import sdpc_create
     from paper_1310_6919_amd.sdpc import sdpc_potrf_static
-    h = sdpc_create(sdpgen.maxcut_band(300, 3, 1.0, 0))   # handle sized for m <= 300
+    # handle sized for m <= 300, with the per-block Cholesky the static entry point runs
+    h = sdpc_create(sdpgen.maxcut_band(300, 3, 1.0, 0), chol_kernel=1)
     rng = np.random.default_rng(2024)
     for m in (300, 130):   # the second call is smaller than the first
         A = sdpgen.random_pd_dense(m, rng, cond=1e3)
