@@ -65,6 +65,31 @@ def test_potrf_matches_lapack(m, kernel):
     h.close()
 
 
+# Many more tiles than the GPU holds resident workgroups (m = 8000: 125 column blocks,
+# about 7900 tasks of the one-launch form), factorised three times each: every run
+# matches LAPACK and the runs agree bit for bit, so no hand-over between tasks reads
+# a tile before it is final.
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_potrf_large_repeatable(kernel):
+    m = 8000
+    rng = np.random.default_rng(8000)
+    G = rng.standard_normal((m, m))
+    A = G @ G.T / m + 0.05 * np.eye(m)
+    Rref = np.linalg.cholesky(A)
+    h = _create(sdpgen.maxcut_band(m, 3, 1.0, 0), chol_kernel=kernel)
+    first = None
+    for _ in range(3):
+        Bt = dev(A.T.copy()).T            # column-major view
+        h.sdpc_potrf(Bt, m)
+        R = np.tril(host(Bt))
+        assert rel_err(R, Rref) <= 1e-12
+        if first is None:
+            first = R
+        else:
+            assert np.array_equal(R, first)
+    h.close()
+
+
 # the failing pivot in each 16-column panel of a block, in the first block and a
 # later one, and the last pivot of a ragged last block
 @pytest.mark.parametrize("kernel", [0, 1])
