@@ -70,6 +70,7 @@ struct sdpc_handle {
     double *Xn = nullptr;   // the next X, formed before the iteration is known to have succeeded
     double *dX = nullptr, *dY = nullptr, *dz = nullptr;
     double *N = nullptr, *Lhat = nullptr, *DinvN = nullptr, *DinvL = nullptr;
+    double *GN = nullptr, *GL = nullptr;   // walk matrices [D_b^{-1}; P21_b D_b^{-1}] of N and Lhat
     double *Dblk = nullptr;   // factorization 1: D of X^ = L^T D L, w x w per storage block (Lhat holds L^{-1})
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
@@ -340,10 +341,11 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     if (m > kMaxM) return fail(h, SDPC_E_PATTERN, "more than " + std::to_string(kMaxM) + " constraints");
     d.solve_generic = h->prm.solve_kernel;
     // ---- block arrays
-    std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size());
+    std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size()), fb(S.bl_rows.size());
     for (size_t t = 0; t < S.bl_rows.size(); ++t) {
         fs[t] = h->slots.fwd[S.bl_rows[t]];
         bs[t] = h->slots.bwd[S.bl_rows[t]];
+        fb[t] = h->slots.birth[S.bl_rows[t]];
     }
     for (int b = 0; b < S.nb; ++b) {
         const int w = S.bl_first[b + 1] - S.bl_first[b];
@@ -695,6 +697,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.bl_subfirst, S.bl_subfirst));
     TRY(upload(h, &d.bl_fslot, fs));
     TRY(upload(h, &d.bl_bslot, bs));
+    TRY(upload(h, &d.bl_fbirth, fb));
     TRY(upload(h, &d.bl_dinv, dinv_off));
     TRY(upload(h, &d.up_ptr, up_ptr));
     TRY(upload(h, &d.up_pair, up_pair));
@@ -770,6 +773,10 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->hcol, size_t(m)));
     TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
+    if (walk_g_ok(d) && h->prm.factorization == 0) {
+        TRY(dalloc(h, &h->GN, size_t(d.nslot)));
+        TRY(dalloc(h, &h->GL, size_t(d.nslot)));
+    }
     if (h->prm.factorization == 1) {
         TRY(dalloc(h, &h->Dblk, size_t(dinv_off.back())));
         HIPCHK(h, hipMemsetAsync(h->Dblk, 0, size_t(dinv_off.back()) * sizeof(double), h->st));
@@ -949,7 +956,7 @@ void launch_xside(sdpc_handle *h, const double *Xbar, int *fail_clique, int *fai
         launch_ldl_cliques(h->d, Xbar, h->Lhat, h->Dblk, fail_clique, h->st);
     else
         launch_algorithm1(h->d, Xbar, h->Lhat, fail_clique, h->st);
-    launch_dinv(h->d, h->Lhat, h->DinvL, fail_dinv, h->st);
+    launch_dinv(h->d, h->Lhat, h->DinvL, fail_dinv, h->st, h->GL);
 }
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
@@ -969,13 +976,14 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     else
         launch_sn_chol(d, Y, h->N, h->ubuf, h->ydw, h->flags + kCand + 5, st);
     h->next_cand = -1;
-    launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st);
+    launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st, h->GN);
     HIPCHK(h, hipEventRecord(h->evs[1], st));
     if (!xready) launch_xside(h, Xbar, h->flags + kCand + 1, h->flags + kCand);
     HIPCHK(h, hipEventRecord(h->evs[2], st));
     // Y^{-1} and X^ in one launch: the two walks are latency-bound and fill each
     // other's idle compute units
-    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st, nullptr, h->Dblk);
+    launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st, nullptr, h->Dblk, h->GN,
+                             h->GL);
     h->xside_ready = false;
     HIPCHK(h, hipEventRecord(h->evs[3], st));
     if (d.hadamard)
@@ -1332,7 +1340,7 @@ sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
     HIPCHK(h, hipMemsetAsync(h->flags + kCand, 0, 8 * sizeof(int), st));
     h->xside_ready = false;
     launch_xside(h, h->X, h->flags + kCand + 1, h->flags + kCand);
-    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st, h->Dblk);
+    launch_inverse_by_solves(d, h->Lhat, h->DinvL, h->Xh, nullptr, nullptr, nullptr, st, h->Dblk, h->GL);
     if (d_Xhat) launch_unpermute(d, h->Xh, d_Xhat, st);
     HIPCHK(h, hipGetLastError());
     int fl[2] = {0, 0};

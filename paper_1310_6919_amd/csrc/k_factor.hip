@@ -331,7 +331,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
 __global__ void __launch_bounds__(64)
 k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
        const int64_t *__restrict__ bl_dinv, const double *__restrict__ L, double *__restrict__ Dinv,
-       int *__restrict__ fail) {
+       int *__restrict__ fail, double *__restrict__ G) {
     __shared__ double D[64 * 64];
     const int b = blockIdx.x;
     const int F = bl_first[b];
@@ -345,9 +345,9 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
     __syncthreads();
     double *X = Dinv + bl_dinv[b];
     const int k = threadIdx.x;
+    double xs[64];   // column k of D^{-1}
     if (k < w) {
         // column k of D^{-1} by forward substitution
-        double xs[64];
         for (int i = 0; i < w; ++i) xs[i] = 0.0;
         const double dk = D[k + w * k];
         if (!(dk != 0.0) || !isfinite(dk)) atomicExch(fail, b + 1);
@@ -358,6 +358,29 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
             xs[i] = -acc / D[i + w * i];
         }
         for (int i = 0; i < w; ++i) X[i + w * k] = xs[i];
+    }
+    if (G && w * h <= 64 * 64) {
+        // G_b = [D^{-1}; P21 D^{-1}] (h x w, column-major at bl_off): D^{-1} (each thread
+        // its column) and P21 staged in LDS over D, then one entry per thread at a time;
+        // D^{-1}(j, c) = 0 for j < c
+        __syncthreads();
+        double *Xs = D, *Ps = D + w * w;
+        const int hw = h - w;
+        if (k < w)
+            for (int i = 0; i < w; ++i) Xs[i + w * k] = xs[i];
+        for (int i = threadIdx.x; i < hw * w; i += blockDim.x) Ps[i] = P[(w + i % hw) + int64_t(h) * (i / hw)];
+        __syncthreads();
+        double *Gb = G + bl_off[b];
+        for (int i = threadIdx.x; i < h * w; i += blockDim.x) {
+            const int r = i % h, c = i / h;
+            double acc = 0.0;
+            if (r < w) {
+                acc = Xs[r + w * c];
+            } else {
+                for (int j = c; j < w; ++j) acc = fma(Ps[(r - w) + hw * j], Xs[j + w * c], acc);
+            }
+            Gb[r + int64_t(h) * c] = acc;
+        }
     }
 }
 
@@ -711,9 +734,9 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
     }
 }
 
-void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st) {
+void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st, double *G) {
     hipLaunchKernelGGL(k_dinv, dim3(d.nb), dim3(64), 0, st, d.bl_first, d.bl_rptr, d.bl_off, d.bl_dinv, L,
-                       Dinv, fail);
+                       Dinv, fail, G);
 }
 
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail, hipStream_t st) {

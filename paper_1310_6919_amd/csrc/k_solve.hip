@@ -27,6 +27,8 @@
 // forward walk gives L e_k, the block-diagonal D (w x w per storage block,
 // zero between supernodes) multiplies each block's part of it before it is
 // stored, and the backward walk applies L^T.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sdpc {
@@ -686,6 +688,222 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same walks with one product per block step.  Per storage block
+//   G_b = [ D_b^{-1} ; P21_b D_b^{-1} ]     (h x w, the panel's layout; k_dinv)
+// holds both halves of a forward step: G_b v_b gives z_b = D_b^{-1} v_b in its first
+// w rows (the forward result) and P21_b z_b in the others (the updates of the rows
+// below).  The backward step is x_b = D_b^{-T} (z_b - P21_b^T x_below) =
+// G_b^T [z_b; -x_below].  Each block step is therefore one MFMA product (16 x 16
+// output tiles, one per wave forward, two waves backward), reading its right-hand
+// side from the LDS slots and writing its results back, then one barrier.  The
+// next block's operands (G, slot ids, the forward result read by the backward step)
+// are loaded into registers in the MFMA layout while the current step runs, so
+// nothing but the pending rows is staged in LDS.
+// Pending forward updates are not zeroed when consumed: every slot records the
+// last block that wrote it, and its value counts only if that block is not older
+// than the first block that updates the slot's current row (blocks a tile skips
+// write nothing).  The host frees a slot one block after its last use (SolveSlots),
+// so no step reads a slot as one of its own rows while writing it as a row below.
+// Limits: every block at most 32 columns wide and 64 rows high.
+struct WalkDesc {
+    int F, w, h, sub;
+    int64_t r0, goff;
+};
+
+constexpr int kWalkWmax = 32, kWalkHmax = 64;
+
+__global__ void __launch_bounds__(kThreads)
+k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
+         const int64_t *__restrict__ bl_off, const int *__restrict__ bl_subfirst, const int *__restrict__ bl_fslot,
+         const int *__restrict__ bl_fbirth, const int *__restrict__ bl_bslot, const int *__restrict__ col_block,
+         int nfwd, int nbwd, const double *__restrict__ G0, double *__restrict__ out0,
+         const double *__restrict__ G1, double *__restrict__ out1) {
+    constexpr int T = kRhs;
+    const double *G = blockIdx.y ? G1 : G0;
+    double *out = blockIdx.y ? out1 : out0;
+    // at least one slot of each kind, so that the clamped slot 0 of a lane without a
+    // slot is always a valid address
+    const int nf1 = max(nfwd, 1), nb1 = max(nbwd, 1);
+    extern __shared__ double sm[];
+    double *accf = sm;                                   // nf1 x T pending forward updates
+    double *accb = accf + size_t(nf1) * T;               // nb1 x T finished backward rows
+    WalkDesc *desc = reinterpret_cast<WalkDesc *>(accb + size_t(nb1) * T);
+    int *lwb = reinterpret_cast<int *>(desc + nb);       // nf1: last block that wrote each slot
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lq = l >> 4;
+    const int k0 = blockIdx.x * T;
+    const int kend = min(n, k0 + T);
+    for (int i = tid; i < nf1; i += kThreads) lwb[i] = -1;
+    for (int b = tid; b < nb; b += kThreads) {
+        WalkDesc e;
+        e.F = bl_first[b];
+        e.w = bl_first[b + 1] - e.F;
+        e.r0 = bl_rptr[b];
+        e.h = int(bl_rptr[b + 1] - e.r0);
+        e.sub = bl_subfirst[b];
+        e.goff = bl_off[b];
+        desc[b] = e;
+    }
+    __syncthreads();
+    auto active = [&](int b) {
+        const WalkDesc &e = desc[b];
+        return !(e.sub > kend - 1 || e.F + e.w - 1 < k0);
+    };
+    auto next_active = [&](int b) {
+        for (++b; b < nb; ++b)
+            if (active(b)) return b;
+        return nb;
+    };
+    // ------------------------------------------------------------ forward
+    // lane operands of a forward step, wave wv owning output rows 16 wv .. 16 wv + 15:
+    // g[ks] = G(16 wv + li, 4 ks + lq); vs / vb: slot and first updating block of
+    // the block's own row 4 ks + lq; os / ob: the same for output row
+    // 16 wv + 4 r + lq.  The loads are clamped into the block and kept raw: what lies
+    // outside the block is masked where the values are used, one step later.  (A
+    // select right after a load lets the compiler move the load into a branch and
+    // wait for it there, which would serialise the prefetch.)
+    struct Fwd {
+        double g[8];
+        int vs[8], vb[8], os[4], ob[4];
+    };
+    auto fetch_fwd = [&](int bb, Fwd &f) {
+        const WalkDesc e = desc[bb];
+        const double *Gb = G + e.goff;
+        const int rowc = min(16 * wv + li, e.h - 1);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int kc = min(4 * ks + lq, e.w - 1);
+            f.g[ks] = Gb[rowc + int64_t(e.h) * kc];
+            f.vs[ks] = bl_fslot[e.r0 + kc];
+            f.vb[ks] = bl_fbirth[e.r0 + kc];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int oc = min(16 * wv + 4 * r + lq, e.h - 1);
+            f.os[r] = bl_fslot[e.r0 + oc];
+            f.ob[r] = bl_fbirth[e.r0 + oc];
+        }
+    };
+    const int b0 = col_block[k0];
+    int b = active(b0) ? b0 : next_active(b0);
+    Fwd cur, nxt;
+    if (b < nb) fetch_fwd(b, cur);
+    while (b < nb) {
+        const int F = desc[b].F, w = desc[b].w, h = desc[b].h;
+        const int bn = next_active(b);
+        fetch_fwd(bn < nb ? bn : b, nxt);   // in flight during this step
+        // v: the pending updates of the block's own rows plus e_k
+        double v[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int k = 4 * ks + lq;
+            const int sv = (k < w) ? cur.vs[ks] : -1;
+            const int sc = max(sv, 0);
+            const double x = accf[sc * T + li];
+            const bool have = sv >= 0 && lwb[sc] >= cur.vb[ks];
+            v[ks] = (have ? x : 0.0) + ((k < w && F + k == k0 + li) ? 1.0 : 0.0);
+        }
+        if (16 * wv < h) {   // uniform
+            const int row = 16 * wv + li;
+            d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+            for (int ks = 0; ks < 8; ks += 2) {
+                const double g0 = (row < h && 4 * ks + lq < w) ? cur.g[ks] : 0.0;
+                const double g1 = (row < h && 4 * ks + 4 + lq < w) ? cur.g[ks + 1] : 0.0;
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0, v[ks], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1, v[ks + 1], a1, 0, 0, 0);
+            }
+            const d4 acc = a0 + a1;
+            // element r: row 16 wv + 4 r + lq of G v, right-hand side li; every lane of a
+            // row reads the row's slot stamp before any of them rewrites it
+            int os[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = 16 * wv + 4 * r + lq;
+                os[r] = (orow >= w && orow < h) ? cur.os[r] : -1;
+                if (orow < w) {
+                    if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
+                } else if (os[r] >= 0) {
+                    const double old = (lwb[os[r]] >= cur.ob[r]) ? accf[os[r] * T + li] : 0.0;
+                    accf[os[r] * T + li] = old - acc[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (os[r] >= 0) lwb[os[r]] = b;
+        }
+        __syncthreads();
+        cur = nxt;
+        b = bn;
+    }
+    // the forward results in `out`, stored by other threads, are read below
+    __syncthreads();
+    // ------------------------------------------------------------ backward
+    // lane operands of a backward step (waves 0, 1: output rows 16 wv .. 16 wv + 15),
+    // raw like the forward ones: ga[ks] = G(4 ks + lq, 16 wv + li); z[ks] = z(4 ks + lq,
+    // li), the forward result of the block's rows; us[ks]: backward slot of row
+    // 4 ks + lq; os[r]: backward slot of output row 16 wv + 4 r + lq
+    struct Bwd {
+        double ga[16], z[8];
+        int us[16], os[4];
+    };
+    auto fetch_bwd = [&](int bb, Bwd &f) {
+        const WalkDesc e = desc[bb];
+        const double *Gb = G + e.goff;
+        const int colc = min(16 * wv + li, e.w - 1);
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int kc = min(4 * ks + lq, e.h - 1);
+            f.ga[ks] = Gb[kc + int64_t(e.h) * colc];
+            f.us[ks] = bl_bslot[e.r0 + kc];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+            f.z[ks] = out[int64_t(n) * min(k0 + li, n - 1) + e.F + min(4 * ks + lq, e.w - 1)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f.os[r] = bl_bslot[e.r0 + min(16 * wv + 4 * r + lq, e.w - 1)];
+    };
+    b = nb - 1;
+    Bwd bc, bx;
+    if (wv < 2) fetch_bwd(b, bc);
+    for (; b >= b0; --b) {
+        const int F = desc[b].F, w = desc[b].w, h = desc[b].h;
+        const bool on = active(b);   // the block was on the forward walk (else z = 0)
+        if (wv < 2) fetch_bwd(b > b0 ? b - 1 : b, bx);
+        if (wv < 2 && 16 * wv < w) {   // uniform
+            const int col = 16 * wv + li;
+            d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+            for (int ks = 0; ks < 16; ks += 2) {
+                double u[2], ga[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int kk = ks + t, k = 4 * kk + lq;
+                    const int sv = (k >= w && k < h) ? bc.us[kk] : -1;
+                    const double x = accb[max(sv, 0) * T + li];
+                    const double zz = (kk < 8 && on && k < w && k0 + li < n) ? bc.z[kk < 8 ? kk : 0] : 0.0;
+                    u[t] = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
+                    ga[t] = (k < h && col < w) ? bc.ga[kk] : 0.0;
+                }
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[0], u[0], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[1], u[1], a1, 0, 0, 0);
+            }
+            const d4 acc = a0 + a1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = 16 * wv + 4 * r + lq;
+                if (orow < w) {
+                    if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
+                    if (bc.os[r] >= 0) accb[bc.os[r] * T + li] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        if (wv < 2) bc = bx;
+    }
+}
+
 // out(j, i) = out(i, j) for i > j, 32 x 32 tiles of the lower triangle
 __global__ void __launch_bounds__(256) k_mirror(int n, double *__restrict__ out0, double *__restrict__ out1) {
     __shared__ double t[32][33];
@@ -717,11 +935,20 @@ size_t solve_lds_mma(const DevStruct &d) {
     return solve_lds(d, kRhs) + sizeof(SolveDesc) * size_t(d.nb);
 }
 
+size_t walk_g_lds(const DevStruct &d) {
+    const size_t nf1 = size_t(std::max(d.nfwd, 1)), nb1 = size_t(std::max(d.nbwd, 1));
+    return sizeof(double) * (nf1 + nb1) * kRhs + sizeof(WalkDesc) * size_t(d.nb) + sizeof(int) * nf1;
+}
+
 bool solve_mma_ok(const DevStruct &d) {
     return d.max_panel <= kPanelMax && d.max_w <= 32 && d.max_h <= kThreads && solve_lds_mma(d) <= 64 * 1024;
 }
 
 }  // namespace
+
+bool walk_g_ok(const DevStruct &d) {
+    return d.max_w <= kWalkWmax && d.max_h <= kWalkHmax && d.bl_fbirth != nullptr && walk_g_lds(d) <= 64 * 1024;
+}
 
 int solve_tile_width(const DevStruct &d) {
     if (d.max_panel > kPanelMax || d.max_w * d.max_w > kDinvMax || d.max_h > kThreads) return 0;
@@ -732,9 +959,16 @@ int solve_tile_width(const DevStruct &d) {
 
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
                               const double *L1, const double *Dinv1, double *out1, hipStream_t st,
-                              const double *Dm0, const double *Dm1) {
+                              const double *Dm0, const double *Dm1, const double *G0, const double *G1) {
     const int nf = L1 ? 2 : 1;
     const int nt = (d.n + 31) / 32;
+    if (!d.solve_generic && G0 && (nf == 1 || G1) && !Dm0 && !Dm1 && walk_g_ok(d)) {
+        hipLaunchKernelGGL(k_walk_g, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), walk_g_lds(d), st, d.n, d.nb,
+                           d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_fbirth, d.bl_bslot,
+                           d.col_block, d.nfwd, d.nbwd, G0, out0, G1, out1);
+        hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
+        return;
+    }
     if (!d.solve_generic && solve_mma_ok(d)) {
         hipLaunchKernelGGL(k_inv_solve_mma, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), solve_lds_mma(d), st,
                            d.n, d.nb, d.max_w, d.max_h, solve_pcap(d), d.bl_first, d.bl_rptr, d.bl_off,

@@ -49,6 +49,7 @@ struct DevStruct {
     const int *bl_subfirst = nullptr;   // nb
     const int *bl_fslot = nullptr;      // sum h: forward solve slot of each row (-1: none)
     const int *bl_bslot = nullptr;      // sum h: backward solve slot of each row (-1: none)
+    const int *bl_fbirth = nullptr;     // sum h: first block that updates each row (-1: none)
     const int64_t *bl_dinv = nullptr;   // nb + 1: offsets of the w x w diagonal-block inverses
     const int64_t *up_ptr = nullptr;    // nb + 1: update pairs of each block
     const int *up_pair = nullptr;       // (a | c << 16), a >= c, indices into the non-own rows
@@ -177,7 +178,11 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
                       hipStream_t st);
 // candidates launched in a round (test points and their gamma twins)
 int dual_step_candidates(int round, int rounds, const int *ntest);
-void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st);
+// Dinv_b = L_bb^{-1} per storage block (w x w at bl_dinv); with G != nullptr also
+// G_b = [L_bb^{-1}; P21_b L_bb^{-1}] (h x w, the panel's layout at bl_off), the one
+// matrix of a block step of the single-product substitution walks
+void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st,
+                 double *G = nullptr);
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,
                        hipStream_t st);
@@ -198,9 +203,13 @@ int solve_tile_width(const DevStruct &d);
 // with Dm_f != nullptr (w x w blocks at bl_dinv, block diagonal over the supernodes)
 // out_f = L_f^{-T} Dm_f L_f^{-1} instead: with L_f^{-1} of eq. sparse_fact as the
 // factor this is X^ = L^T D L
+// With G0 (and G1 for a second factor) from launch_dinv, no Dm and every block at
+// most 32 wide and 64 high, the walks take one product per block step (walk_g_ok).
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
                               const double *L1, const double *Dinv1, double *out1, hipStream_t st,
-                              const double *Dm0 = nullptr, const double *Dm1 = nullptr);
+                              const double *Dm0 = nullptr, const double *Dm1 = nullptr,
+                              const double *G0 = nullptr, const double *G1 = nullptr);
+bool walk_g_ok(const DevStruct &d);
 
 // ---- Schur complement (k_scm.hip)
 void launch_scm_hadamard(const DevStruct &d, const double *Xh, const double *Yi, double *B,

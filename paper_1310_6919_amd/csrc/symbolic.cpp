@@ -305,15 +305,16 @@ SolveSlots build_solve_slots(const Symbolic &S) {
         std::priority_queue<int, std::vector<int>, std::greater<int>> freel;
         int used = 0;
         for (int b = 0; b < S.nb; ++b) {
-            for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j)   // released first
-                if (R.fwd[j] >= 0) freel.push(R.fwd[j]);
             for (int i : born[b]) {
                 int s;
                 if (!freel.empty()) { s = freel.top(); freel.pop(); } else { s = used++; }
                 R.fwd[i] = s;
             }
+            for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j)   // free from block b + 1 on
+                if (R.fwd[j] >= 0) freel.push(R.fwd[j]);
         }
         R.nfwd = used;
+        R.birth = first_touch;
     }
     {
         // backward sweep runs b = nb-1 .. 0; row i is born at its own block and
@@ -324,13 +325,13 @@ SolveSlots build_solve_slots(const Symbolic &S) {
         std::priority_queue<int, std::vector<int>, std::greater<int>> freel;
         int used = 0;
         for (int b = S.nb - 1; b >= 0; --b) {
-            for (int i : dies[b]) freel.push(R.bwd[i]);              // read at b, then free
             for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j) {
                 if (last_read[j] < 0) continue;
                 int s;
                 if (!freel.empty()) { s = freel.top(); freel.pop(); } else { s = used++; }
                 R.bwd[j] = s;
             }
+            for (int i : dies[b]) freel.push(R.bwd[i]);              // read at b, free from b - 1 on
         }
         R.nbwd = used;
     }
