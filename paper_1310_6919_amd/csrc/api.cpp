@@ -341,11 +341,10 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     if (m > kMaxM) return fail(h, SDPC_E_PATTERN, "more than " + std::to_string(kMaxM) + " constraints");
     d.solve_generic = h->prm.solve_kernel;
     // ---- block arrays
-    std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size()), fb(S.bl_rows.size());
+    std::vector<int> fs(S.bl_rows.size()), bs(S.bl_rows.size());
     for (size_t t = 0; t < S.bl_rows.size(); ++t) {
         fs[t] = h->slots.fwd[S.bl_rows[t]];
         bs[t] = h->slots.bwd[S.bl_rows[t]];
-        fb[t] = h->slots.birth[S.bl_rows[t]];
     }
     for (int b = 0; b < S.nb; ++b) {
         const int w = S.bl_first[b + 1] - S.bl_first[b];
@@ -697,7 +696,21 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.bl_subfirst, S.bl_subfirst));
     TRY(upload(h, &d.bl_fslot, fs));
     TRY(upload(h, &d.bl_bslot, bs));
-    TRY(upload(h, &d.bl_fbirth, fb));
+    if (S.max_w <= 32 && S.max_h <= 64) {
+        // the single-product walks' per-block row lists: row r at (r % 4) * 16 + r / 4
+        std::vector<int> tfs(size_t(S.nb) * 64, -1), tfb(size_t(S.nb) * 64, -1), tbs(size_t(S.nb) * 64, -1);
+        for (int b = 0; b < S.nb; ++b)
+            for (int64_t t = S.bl_rptr[b]; t < S.bl_rptr[b + 1]; ++t) {
+                const int r = int(t - S.bl_rptr[b]);
+                const size_t idx = size_t(b) * 64 + size_t(r % 4) * 16 + size_t(r / 4);
+                tfs[idx] = fs[t];
+                tfb[idx] = h->slots.birth[S.bl_rows[t]];
+                tbs[idx] = bs[t];
+            }
+        TRY(upload(h, &d.wk_fs, tfs));
+        TRY(upload(h, &d.wk_fb, tfb));
+        TRY(upload(h, &d.wk_bs, tbs));
+    }
     TRY(upload(h, &d.bl_dinv, dinv_off));
     TRY(upload(h, &d.up_ptr, up_ptr));
     TRY(upload(h, &d.up_pair, up_pair));
@@ -774,8 +787,8 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
     if (walk_g_ok(d) && h->prm.factorization == 0) {
-        TRY(dalloc(h, &h->GN, size_t(d.nslot)));
-        TRY(dalloc(h, &h->GL, size_t(d.nslot)));
+        TRY(dalloc(h, &h->GN, size_t(d.nb) * 4096));
+        TRY(dalloc(h, &h->GL, size_t(d.nb) * 4096));
     }
     if (h->prm.factorization == 1) {
         TRY(dalloc(h, &h->Dblk, size_t(dinv_off.back())));

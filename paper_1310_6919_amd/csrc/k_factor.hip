@@ -359,18 +359,19 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
         }
         for (int i = 0; i < w; ++i) X[i + w * k] = xs[i];
     }
-    if (G && w * h <= 64 * 64) {
-        // G_b = [D^{-1}; P21 D^{-1}] (h x w, column-major at bl_off): D^{-1} (each thread
-        // its column) and P21 staged in LDS over D, then one entry per thread at a time;
-        // D^{-1}(j, c) = 0 for j < c
+    if (G && w <= 32 && h <= 64) {
+        // G_b = [D^{-1}; P21 D^{-1}] (h x w): D^{-1} (each thread its column), P21 and G
+        // in LDS over D (w h <= 2048 doubles each part), D^{-1}(j, c) = 0 for j < c;
+        // then stored in the walks' lane order, zero outside the block:
+        //   forward  (wave f < 4, lane l, ks < 8):  G(16 f + l % 16, 4 ks + l / 16)
+        //   backward (wave f < 2, lane l, ks < 16): G(4 ks + l / 16, 16 f + l % 16)
         __syncthreads();
-        double *Xs = D, *Ps = D + w * w;
+        double *Xs = D, *Ps = D + w * w, *Gs = D + 2048;
         const int hw = h - w;
         if (k < w)
             for (int i = 0; i < w; ++i) Xs[i + w * k] = xs[i];
         for (int i = threadIdx.x; i < hw * w; i += blockDim.x) Ps[i] = P[(w + i % hw) + int64_t(h) * (i / hw)];
         __syncthreads();
-        double *Gb = G + bl_off[b];
         for (int i = threadIdx.x; i < h * w; i += blockDim.x) {
             const int r = i % h, c = i / h;
             double acc = 0.0;
@@ -379,7 +380,19 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
             } else {
                 for (int j = c; j < w; ++j) acc = fma(Ps[(r - w) + hw * j], Xs[j + w * c], acc);
             }
-            Gb[r + int64_t(h) * c] = acc;
+            Gs[r + h * c] = acc;
+        }
+        __syncthreads();
+        double *Gb = G + size_t(b) * 4096;
+        for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
+            const int ks = i % 8, l = (i / 8) % 64, f = i / 512;
+            const int r = 16 * f + l % 16, c = 4 * ks + l / 16;
+            Gb[i] = (r < h && c < w) ? Gs[r + h * c] : 0.0;
+        }
+        for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
+            const int ks = i % 16, l = (i / 16) % 64, f = i / 1024;
+            const int r = 4 * ks + l / 16, c = 16 * f + l % 16;
+            Gb[2048 + i] = (r < h && c < w) ? Gs[r + h * c] : 0.0;
         }
     }
 }

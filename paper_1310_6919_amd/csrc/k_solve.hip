@@ -708,17 +708,17 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
 // Limits: every block at most 32 columns wide and 64 rows high.
 struct WalkDesc {
     int F, w, h, sub;
-    int64_t r0, goff;
 };
 
 constexpr int kWalkWmax = 32, kWalkHmax = 64;
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kThreads)
 k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
-         const int64_t *__restrict__ bl_off, const int *__restrict__ bl_subfirst, const int *__restrict__ bl_fslot,
-         const int *__restrict__ bl_fbirth, const int *__restrict__ bl_bslot, const int *__restrict__ col_block,
-         int nfwd, int nbwd, const double *__restrict__ G0, double *__restrict__ out0,
-         const double *__restrict__ G1, double *__restrict__ out1) {
+         const int *__restrict__ bl_subfirst, const int *__restrict__ wk_fs, const int *__restrict__ wk_fb,
+         const int *__restrict__ wk_bs, const int *__restrict__ col_block, int nfwd, int nbwd,
+         const double *__restrict__ G0, double *__restrict__ out0, const double *__restrict__ G1,
+         double *__restrict__ out1) {
     constexpr int T = kRhs;
     const double *G = blockIdx.y ? G1 : G0;
     double *out = blockIdx.y ? out1 : out0;
@@ -739,10 +739,8 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
         WalkDesc e;
         e.F = bl_first[b];
         e.w = bl_first[b + 1] - e.F;
-        e.r0 = bl_rptr[b];
-        e.h = int(bl_rptr[b + 1] - e.r0);
+        e.h = int(bl_rptr[b + 1] - bl_rptr[b]);
         e.sub = bl_subfirst[b];
-        e.goff = bl_off[b];
         desc[b] = e;
     }
     __syncthreads();
@@ -756,33 +754,33 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
         return nb;
     };
     // ------------------------------------------------------------ forward
-    // lane operands of a forward step, wave wv owning output rows 16 wv .. 16 wv + 15:
-    // g[ks] = G(16 wv + li, 4 ks + lq); vs / vb: slot and first updating block of
-    // the block's own row 4 ks + lq; os / ob: the same for output row
-    // 16 wv + 4 r + lq.  The loads are clamped into the block and kept raw: what lies
-    // outside the block is masked where the values are used, one step later.  (A
-    // select right after a load lets the compiler move the load into a branch and
-    // wait for it there, which would serialise the prefetch.)
+    // lane operands of a forward step, wave wv owning output rows 16 wv .. 16 wv + 15,
+    // each a few contiguous vector loads from the lane-ordered G and row lists (zero
+    // and -1 outside the block): g[ks] = G(16 wv + li, 4 ks + lq); vs / vb: slot and
+    // first updating block of row 4 ks + lq; os / ob: the same for row 16 wv + 4 r + lq
     struct Fwd {
         double g[8];
         int vs[8], vb[8], os[4], ob[4];
     };
     auto fetch_fwd = [&](int bb, Fwd &f) {
-        const WalkDesc e = desc[bb];
-        const double *Gb = G + e.goff;
-        const int rowc = min(16 * wv + li, e.h - 1);
+        const double2 *gp = reinterpret_cast<const double2 *>(G + size_t(bb) * 4096 + size_t(wv * 64 + l) * 8);
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int kc = min(4 * ks + lq, e.w - 1);
-            f.g[ks] = Gb[rowc + int64_t(e.h) * kc];
-            f.vs[ks] = bl_fslot[e.r0 + kc];
-            f.vb[ks] = bl_fbirth[e.r0 + kc];
+        for (int u = 0; u < 4; ++u) {
+            const double2 t = gp[u];
+            f.g[2 * u] = t.x;
+            f.g[2 * u + 1] = t.y;
         }
+        const i4 *fsp = reinterpret_cast<const i4 *>(wk_fs + size_t(bb) * 64 + lq * 16);
+        const i4 *fbp = reinterpret_cast<const i4 *>(wk_fb + size_t(bb) * 64 + lq * 16);
+        const i4 s0 = fsp[0], s1 = fsp[1], so = fsp[wv], b0v = fbp[0], b1v = fbp[1], bo = fbp[wv];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int oc = min(16 * wv + 4 * r + lq, e.h - 1);
-            f.os[r] = bl_fslot[e.r0 + oc];
-            f.ob[r] = bl_fbirth[e.r0 + oc];
+        for (int u = 0; u < 4; ++u) {
+            f.vs[u] = s0[u];
+            f.vs[4 + u] = s1[u];
+            f.vb[u] = b0v[u];
+            f.vb[4 + u] = b1v[u];
+            f.os[u] = so[u];
+            f.ob[u] = bo[u];
         }
     };
     const int b0 = col_block[k0];
@@ -805,14 +803,11 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
             v[ks] = (have ? x : 0.0) + ((k < w && F + k == k0 + li) ? 1.0 : 0.0);
         }
         if (16 * wv < h) {   // uniform
-            const int row = 16 * wv + li;
             d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
 #pragma unroll
             for (int ks = 0; ks < 8; ks += 2) {
-                const double g0 = (row < h && 4 * ks + lq < w) ? cur.g[ks] : 0.0;
-                const double g1 = (row < h && 4 * ks + 4 + lq < w) ? cur.g[ks + 1] : 0.0;
-                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(g0, v[ks], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(g1, v[ks + 1], a1, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks], v[ks], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks + 1], v[ks + 1], a1, 0, 0, 0);
             }
             const d4 acc = a0 + a1;
             // element r: row 16 wv + 4 r + lq of G v, right-hand side li; every lane of a
@@ -821,12 +816,13 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int orow = 16 * wv + 4 * r + lq;
-                os[r] = (orow >= w && orow < h) ? cur.os[r] : -1;
+                os[r] = (orow >= w) ? cur.os[r] : -1;   // -1 beyond the block already
+                const int sc = max(os[r], 0);
+                const double old = (os[r] >= 0 && lwb[sc] >= cur.ob[r]) ? accf[sc * T + li] : 0.0;
                 if (orow < w) {
                     if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
                 } else if (os[r] >= 0) {
-                    const double old = (lwb[os[r]] >= cur.ob[r]) ? accf[os[r] * T + li] : 0.0;
-                    accf[os[r] * T + li] = old - acc[r];
+                    accf[sc * T + li] = old - acc[r];
                 }
             }
 #pragma unroll
@@ -840,63 +836,114 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
     // the forward results in `out`, stored by other threads, are read below
     __syncthreads();
     // ------------------------------------------------------------ backward
-    // lane operands of a backward step (waves 0, 1: output rows 16 wv .. 16 wv + 15),
-    // raw like the forward ones: ga[ks] = G(4 ks + lq, 16 wv + li); z[ks] = z(4 ks + lq,
-    // li), the forward result of the block's rows; us[ks]: backward slot of row
-    // 4 ks + lq; os[r]: backward slot of output row 16 wv + 4 r + lq
+    // Waves 0, 1 compute (output rows 16 wv .. 16 wv + 15) from lane-ordered operands:
+    // ga[ks] = G(4 ks + lq, 16 wv + li); us[ks]: backward slot of row 4 ks + lq; os[r]:
+    // backward slot of output row 16 wv + 4 r + lq.
+    // Waves 2, 3 load the forward results z of the blocks to come: the columns of
+    // `out` lie n doubles apart and were written long before, so these loads miss in
+    // L2.  Block q's z is loaded at the step of block q + 3 (register set q & 1),
+    // written into the LDS ring slot q & 1 at the step of block q + 1, and read at
+    // the step of block q; zero where the block was not on the forward walk.
     struct Bwd {
-        double ga[16], z[8];
+        double ga[16];
         int us[16], os[4];
     };
     auto fetch_bwd = [&](int bb, Bwd &f) {
-        const WalkDesc e = desc[bb];
-        const double *Gb = G + e.goff;
-        const int colc = min(16 * wv + li, e.w - 1);
+        const double2 *gp =
+            reinterpret_cast<const double2 *>(G + size_t(bb) * 4096 + 2048 + size_t(wv * 64 + l) * 16);
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int kc = min(4 * ks + lq, e.h - 1);
-            f.ga[ks] = Gb[kc + int64_t(e.h) * colc];
-            f.us[ks] = bl_bslot[e.r0 + kc];
+        for (int u = 0; u < 8; ++u) {
+            const double2 t = gp[u];
+            f.ga[2 * u] = t.x;
+            f.ga[2 * u + 1] = t.y;
         }
+        const i4 *bsp = reinterpret_cast<const i4 *>(wk_bs + size_t(bb) * 64 + lq * 16);
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-            f.z[ks] = out[int64_t(n) * min(k0 + li, n - 1) + e.F + min(4 * ks + lq, e.w - 1)];
+        for (int u = 0; u < 4; ++u) {
+            const i4 t = bsp[u];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) f.os[r] = bl_bslot[e.r0 + min(16 * wv + 4 * r + lq, e.w - 1)];
+            for (int j = 0; j < 4; ++j) f.us[4 * u + j] = t[j];
+        }
+        const i4 to = bsp[wv];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f.os[j] = to[j];
     };
+    constexpr int ZLD = 33;   // ring slot: z(k, c) at c * ZLD + k, 16 x 32
+    double *zr = reinterpret_cast<double *>(lwb + nf1 + (nf1 & 1));
+    const int lt = tid - 128;   // loader thread (waves 2, 3): entries lt + 128 j, row k = e % 32, column c = e / 32
+    auto zload = [&](int q, double (&zs)[4]) {
+        const WalkDesc e = desc[q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ent = lt + 128 * j, k = ent & 31, c = ent >> 5;
+            zs[j] = out[int64_t(n) * min(k0 + c, n - 1) + e.F + min(k, e.w - 1)];
+        }
+    };
+    auto zwrite = [&](int q, const double (&zs)[4]) {
+        const WalkDesc e = desc[q];
+        const bool on = active(q);
+        double *zslot = zr + (q & 1) * (16 * ZLD);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ent = lt + 128 * j, k = ent & 31, c = ent >> 5;
+            zslot[c * ZLD + k] = (on && k < e.w && k0 + c < n) ? zs[j] : 0.0;
+        }
+    };
+    double zs0[4], zs1[4];   // loader register sets: block q in set q & 1
     b = nb - 1;
     Bwd bc, bx;
-    if (wv < 2) fetch_bwd(b, bc);
+    if (wv < 2) {
+        fetch_bwd(b, bc);
+    } else {
+        if (b & 1) zload(b, zs1); else zload(b, zs0);
+        if (b - 1 >= b0) {
+            if ((b - 1) & 1) zload(b - 1, zs1); else zload(b - 1, zs0);
+        }
+        if (b & 1) zwrite(b, zs1); else zwrite(b, zs0);
+        if (b - 2 >= b0) {
+            if (b & 1) zload(b - 2, zs1); else zload(b - 2, zs0);
+        }
+    }
+    __syncthreads();
     for (; b >= b0; --b) {
-        const int F = desc[b].F, w = desc[b].w, h = desc[b].h;
-        const bool on = active(b);   // the block was on the forward walk (else z = 0)
-        if (wv < 2) fetch_bwd(b > b0 ? b - 1 : b, bx);
-        if (wv < 2 && 16 * wv < w) {   // uniform
-            const int col = 16 * wv + li;
-            d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+        const int F = desc[b].F, w = desc[b].w;
+        if (wv < 2) {
+            fetch_bwd(b > b0 ? b - 1 : b, bx);
+            if (16 * wv < w) {   // uniform
+                const double *zslot = zr + (b & 1) * (16 * ZLD);
+                d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
 #pragma unroll
-            for (int ks = 0; ks < 16; ks += 2) {
-                double u[2], ga[2];
+                for (int ks = 0; ks < 16; ks += 2) {
+                    double u[2];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int kk = ks + t, k = 4 * kk + lq;
-                    const int sv = (k >= w && k < h) ? bc.us[kk] : -1;
-                    const double x = accb[max(sv, 0) * T + li];
-                    const double zz = (kk < 8 && on && k < w && k0 + li < n) ? bc.z[kk < 8 ? kk : 0] : 0.0;
-                    u[t] = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
-                    ga[t] = (k < h && col < w) ? bc.ga[kk] : 0.0;
+                    for (int t = 0; t < 2; ++t) {
+                        const int kk = ks + t, k = 4 * kk + lq;
+                        const int sv = (k >= w) ? bc.us[kk] : -1;   // -1 beyond the block already
+                        const double x = accb[max(sv, 0) * T + li];
+                        const double zz = (kk < 8) ? zslot[li * ZLD + (kk < 8 ? k : 0)] : 0.0;
+                        u[t] = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
+                    }
+                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[ks], u[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[ks + 1], u[1], a1, 0, 0, 0);
                 }
-                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[0], u[0], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[1], u[1], a1, 0, 0, 0);
+                const d4 acc = a0 + a1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int orow = 16 * wv + 4 * r + lq;
+                    if (orow < w) {
+                        if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
+                        if (bc.os[r] >= 0) accb[bc.os[r] * T + li] = acc[r];
+                    }
+                }
             }
-            const d4 acc = a0 + a1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int orow = 16 * wv + 4 * r + lq;
-                if (orow < w) {
-                    if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
-                    if (bc.os[r] >= 0) accb[bc.os[r] * T + li] = acc[r];
-                }
+        } else if (b - 1 >= b0) {
+            // write block b - 1's z (set (b - 1) & 1), then load block b - 3 into that set
+            if ((b - 1) & 1) {
+                zwrite(b - 1, zs1);
+                if (b - 3 >= b0) zload(b - 3, zs1);
+            } else {
+                zwrite(b - 1, zs0);
+                if (b - 3 >= b0) zload(b - 3, zs0);
             }
         }
         __syncthreads();
@@ -937,7 +984,8 @@ size_t solve_lds_mma(const DevStruct &d) {
 
 size_t walk_g_lds(const DevStruct &d) {
     const size_t nf1 = size_t(std::max(d.nfwd, 1)), nb1 = size_t(std::max(d.nbwd, 1));
-    return sizeof(double) * (nf1 + nb1) * kRhs + sizeof(WalkDesc) * size_t(d.nb) + sizeof(int) * nf1;
+    return sizeof(double) * (nf1 + nb1) * kRhs + sizeof(WalkDesc) * size_t(d.nb) + sizeof(int) * (nf1 + (nf1 & 1)) +
+           sizeof(double) * 2 * 16 * 33;   // the ring of forward results read by the backward walk
 }
 
 bool solve_mma_ok(const DevStruct &d) {
@@ -947,7 +995,7 @@ bool solve_mma_ok(const DevStruct &d) {
 }  // namespace
 
 bool walk_g_ok(const DevStruct &d) {
-    return d.max_w <= kWalkWmax && d.max_h <= kWalkHmax && d.bl_fbirth != nullptr && walk_g_lds(d) <= 64 * 1024;
+    return d.max_w <= kWalkWmax && d.max_h <= kWalkHmax && d.wk_fs != nullptr && walk_g_lds(d) <= 64 * 1024;
 }
 
 int solve_tile_width(const DevStruct &d) {
@@ -964,8 +1012,8 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
     const int nt = (d.n + 31) / 32;
     if (!d.solve_generic && G0 && (nf == 1 || G1) && !Dm0 && !Dm1 && walk_g_ok(d)) {
         hipLaunchKernelGGL(k_walk_g, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), walk_g_lds(d), st, d.n, d.nb,
-                           d.bl_first, d.bl_rptr, d.bl_off, d.bl_subfirst, d.bl_fslot, d.bl_fbirth, d.bl_bslot,
-                           d.col_block, d.nfwd, d.nbwd, G0, out0, G1, out1);
+                           d.bl_first, d.bl_rptr, d.bl_subfirst, d.wk_fs, d.wk_fb, d.wk_bs, d.col_block, d.nfwd,
+                           d.nbwd, G0, out0, G1, out1);
         hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
         return;
     }

@@ -49,7 +49,10 @@ struct DevStruct {
     const int *bl_subfirst = nullptr;   // nb
     const int *bl_fslot = nullptr;      // sum h: forward solve slot of each row (-1: none)
     const int *bl_bslot = nullptr;      // sum h: backward solve slot of each row (-1: none)
-    const int *bl_fbirth = nullptr;     // sum h: first block that updates each row (-1: none)
+    // the single-product walks (blocks <= 32 wide, <= 64 high): per block 64 entries
+    // for its rows r in the order (r % 4) * 16 + r / 4, -1 beyond the block: forward
+    // slot, first block that updates the row, backward slot
+    const int *wk_fs = nullptr, *wk_fb = nullptr, *wk_bs = nullptr;
     const int64_t *bl_dinv = nullptr;   // nb + 1: offsets of the w x w diagonal-block inverses
     const int64_t *up_ptr = nullptr;    // nb + 1: update pairs of each block
     const int *up_pair = nullptr;       // (a | c << 16), a >= c, indices into the non-own rows
@@ -179,8 +182,9 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
 // candidates launched in a round (test points and their gamma twins)
 int dual_step_candidates(int round, int rounds, const int *ntest);
 // Dinv_b = L_bb^{-1} per storage block (w x w at bl_dinv); with G != nullptr also
-// G_b = [L_bb^{-1}; P21_b L_bb^{-1}] (h x w, the panel's layout at bl_off), the one
-// matrix of a block step of the single-product substitution walks
+// G_b = [L_bb^{-1}; P21_b L_bb^{-1}] (h x w), the one matrix of a block step of the
+// single-product substitution walks, at G + 4096 b in the walks' lane order
+// (walk_g_layout); needs w <= 32 and h <= 64
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st,
                  double *G = nullptr);
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
