@@ -56,7 +56,8 @@ struct sdpc_handle {
     int n = 0, m = 0;
     sdpc_params prm{};
     Symbolic S;
-    SolveSlots slots;
+    SolveSlots slots;    // the multi-right-hand-side substitutions
+    SolveSlots wslots;   // the single-product walks (slots freed one block late)
     DevStruct d;
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -279,10 +280,13 @@ static sdpc_status analyze_impl(const sdpc_problem *prob, sdpc_handle *h, std::v
         return fail(h, SDPC_E_PATTERN, "largest clique has " + std::to_string(S.max_clique) + " members (limit " +
                                            std::to_string(kMaxClique) + ")");
     if (S.nslot >= (int64_t(1) << 31)) return fail(h, SDPC_E_PATTERN, "storage exceeds 2^31 entries");
-    h->slots = build_solve_slots(S);
+    h->slots = build_solve_slots(S, false);
+    h->wslots = build_solve_slots(S, true);
     h->d.n = n;
     h->d.nfwd = h->slots.nfwd;
     h->d.nbwd = h->slots.nbwd;
+    h->d.wk_nfwd = h->wslots.nfwd;
+    h->d.wk_nbwd = h->wslots.nbwd;
     h->d.max_h = S.max_h;
     h->d.max_w = S.max_w;
     h->d.max_panel = 0;
@@ -396,15 +400,15 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             }
         }
         // the pool is used when the factorisation's LDS stays within the budget (32 KiB by
-        // default: four waves per compute unit)
+        // default: four waves per compute unit); one more slot stays zero
         d.u_pool = (h->prm.pool_lds_bytes > 0 &&
-                    wave_chol_lds_bytes(S.max_h, used) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
+                    wave_chol_lds_bytes(S.max_h, used + 1) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
         if (!d.u_pool) {   // one slot per target entry, in global memory
             int k = 0;
             for (int64_t s = 0; s < S.nslot; ++s)
                 if (born_at[s] >= 0) slot_u[s] = k++;
         }
-        d.nU = d.u_pool ? used : ntarget;
+        d.nU = (d.u_pool ? used : ntarget) + 1;
         std::vector<uint8_t> seen(size_t(S.nslot), 0);
         for (int b = 0; b < S.nb; ++b)
             for (int64_t t = up_ptr[b]; t < up_ptr[b + 1]; ++t) {
@@ -419,20 +423,54 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         for (int64_t s = 0; s < S.nslot; ++s)
             if (!S.isE[s]) slot_u[s] = (slot_u[s] >= 0) ? -3 - slot_u[s] : -2;
     }
-    // the same codes per 64 x 32 panel tile, row-major (the one-wave factorisation's
-    // read order), -2 outside the panel
+    // the slot each panel entry adds (the last, zero, slot where there is no update or
+    // outside the panel) per 64 x 32 panel tile, in the one-wave factorisation's read
+    // order: per group of four columns, per row, the four slots
     std::vector<int> su_rows;
     if (S.max_h <= 64 && S.max_w <= 32) {
-        su_rows.assign(size_t(S.nb) * 64 * 32, -2);
+        const int zero = int(d.nU - 1);
+        su_rows.assign(size_t(S.nb) * 64 * 32, zero);
         for (int b = 0; b < S.nb; ++b) {
             const int w = S.bl_first[b + 1] - S.bl_first[b];
             const int hh = int(S.bl_rptr[b + 1] - S.bl_rptr[b]);
             for (int i = 0; i < hh; ++i)
-                for (int k = 0; k < w; ++k)
-                    su_rows[(size_t(b) * 64 + i) * 32 + k] = slot_u[S.bl_off[b] + i + int64_t(hh) * k];
+                for (int k = 0; k < w; ++k) {
+                    const int v = slot_u[S.bl_off[b] + i + int64_t(hh) * k];
+                    su_rows[((size_t(b) * 8 + k / 4) * 64 + i) * 4 + k % 4] = v >= 0 ? v : (v <= -3 ? -3 - v : zero);
+                }
         }
     } else {
         su_rows.assign(1, -2);
+    }
+    // the update codes in the MFMA lane order, and the block sizes
+    std::vector<int> wc_meta(size_t(S.nb) * 4, 0), wc_up(1, -1);
+    if (S.max_h <= 64 && S.max_w <= 32) {
+        int hpmax = 0;
+        for (int b = 0; b < S.nb; ++b) {
+            const int w = S.bl_first[b + 1] - S.bl_first[b];
+            const int hh = int(S.bl_rptr[b + 1] - S.bl_rptr[b]);
+            hpmax = std::max(hpmax, hh - w);
+            wc_meta[size_t(b) * 4] = w;
+            wc_meta[size_t(b) * 4 + 1] = hh;
+            wc_meta[size_t(b) * 4 + 2] = int(S.bl_off[b]);
+        }
+        d.wc_rt = hpmax <= 32 ? 2 : 4;
+        const int rt = d.wc_rt, mt = rt * (rt + 1) / 2;
+        wc_up.assign(size_t(S.nb) * mt * 64 * 4, -1);
+        for (int b = 0; b < S.nb; ++b) {
+            const int hp = int(S.bl_rptr[b + 1] - S.bl_rptr[b]) - (S.bl_first[b + 1] - S.bl_first[b]);
+            // pair (a, c), a >= c: up_ptr[b] + c hp - c (c - 1) / 2 + (a - c)
+            auto code = [&](int a, int c) {
+                if (a >= hp || c >= hp || a < c) return -1;
+                return up_u[size_t(up_ptr[b] + int64_t(c) * hp - int64_t(c) * (c - 1) / 2 + (a - c))];
+            };
+            int t = 0;
+            for (int ti = 0; ti < rt; ++ti)
+                for (int tj = 0; tj <= ti; ++tj, ++t)
+                    for (int l = 0; l < 64; ++l)
+                        for (int r = 0; r < 4; ++r)
+                            wc_up[((size_t(b) * mt + t) * 64 + l) * 4 + r] = code(16 * ti + 4 * r + l / 16, 16 * tj + l % 16);
+        }
     }
     // ---- cliques
     std::vector<int64_t> cl_ptr(S.ncl + 1, 0), cl_map_ptr(S.ncl + 1, 0);
@@ -703,9 +741,9 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             for (int64_t t = S.bl_rptr[b]; t < S.bl_rptr[b + 1]; ++t) {
                 const int r = int(t - S.bl_rptr[b]);
                 const size_t idx = size_t(b) * 64 + size_t(r % 4) * 16 + size_t(r / 4);
-                tfs[idx] = fs[t];
-                tfb[idx] = h->slots.birth[S.bl_rows[t]];
-                tbs[idx] = bs[t];
+                tfs[idx] = h->wslots.fwd[S.bl_rows[t]];
+                tfb[idx] = h->wslots.birth[S.bl_rows[t]];
+                tbs[idx] = h->wslots.bwd[S.bl_rows[t]];
             }
         TRY(upload(h, &d.wk_fs, tfs));
         TRY(upload(h, &d.wk_fb, tfb));
@@ -715,9 +753,9 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.up_ptr, up_ptr));
     TRY(upload(h, &d.up_pair, up_pair));
     TRY(upload(h, &d.up_slot, up_slot));
-    TRY(upload(h, &d.up_u, up_u));
-    TRY(upload(h, &d.slot_u, slot_u));
     TRY(upload(h, &d.su_rows, su_rows));
+    TRY(upload(h, &d.wc_meta, wc_meta));
+    TRY(upload(h, &d.wc_up, wc_up));
     TRY(upload(h, &d.col_block, S.col_block));
     TRY(upload(h, &d.slot_row, slot_row));
     TRY(upload(h, &d.slot_col, slot_col));

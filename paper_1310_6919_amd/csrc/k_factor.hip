@@ -151,58 +151,66 @@ k_sn_chol(int nb, int64_t nslot, const double *__restrict__ wE, const int *__res
     if (tid == 0) fail[cand] = 0;
 }
 
-// (Y, dY) of every storage block as a 64 x 32 row-major tile of pairs (zeros
-// outside the panel; dY == nullptr gives dy = 0), the layout in which the one-wave
-// factorisation reads a panel row per lane with 16-byte loads.
+// (Y, dY) of every storage block as a 64 x 32 column-major tile of pairs (zeros
+// outside the panel and on its padding slots, which start from zero; dY == nullptr
+// gives dy = 0): the one-wave factorisation reads a panel row per lane, each load
+// one column of 64 consecutive pairs.
 __global__ void __launch_bounds__(256)
 k_yd_rows(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
-          const double *__restrict__ Y, const double *__restrict__ dY, double2 *__restrict__ yd) {
+          const double *__restrict__ wE, const double *__restrict__ Y, const double *__restrict__ dY,
+          double2 *__restrict__ yd) {
     const int b = blockIdx.x;
     const int w = bl_first[b + 1] - bl_first[b];
     const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
     const int64_t off = bl_off[b];
     for (int e = threadIdx.x; e < 64 * 32; e += blockDim.x) {
-        const int i = e / 32, k = e % 32;
+        const int i = e % 64, k = e / 64;
         double2 v = double2{0.0, 0.0};
         if (i < h && k < w) {
             const int64_t s = off + i + int64_t(h) * k;
-            v = double2{Y[s], dY ? dY[s] : 0.0};
+            if (wE[s] != 0.0) v = double2{Y[s], dY ? dY[s] : 0.0};
         }
         yd[size_t(b) * 64 * 32 + e] = v;
     }
 }
 
 // Y = N N^T on the storage blocks by a single wave (panels of at most 64 rows and
-// 32 columns).  Lane i holds row i of the panel in registers; the pivot and the
-// scaled pivot column reach the other lanes through readlane, so the elimination
-// needs neither LDS nor barriers.  The update of the ancestors, N(U, U) -=
-// L21 L21^T, takes its operands from LDS (rows of L21, row-major).
+// 32 columns).  Lane i holds row i of the panel in registers.  The elimination
+// broadcasts the pivot and the next column's multiplier by readlane and the other
+// multipliers through a 64-double LDS buffer (elim_lds).  The update of the
+// ancestors, N(U, U) -= L21 L21^T, runs on the FP64 MFMA: L21 (at most 16 RT rows,
+// row-major in LDS) is cut into RT row tiles and every lower tile pair is one
+// chain of eight 16 x 16 x 4 products; wc_up gives, in the MFMA's lane order, the
+// pending-update slot code of each result element (-1 where there is none: above
+// the diagonal, outside the structure, padding rows).
 // blockIdx.x selects the candidate Y + alpha_c dY (dual == false: Y itself).  The
 // candidate is never written out: a panel is formed when its block is reached,
 // from Y and dY (copied per panel row-major by k_yd_rows, read one block ahead
 // while the previous block is factorised) and the pending updates of its
-// descendants.  Those live in slots (slot_u maps
-// a storage slot to its slot: -1 if it receives no update; on padding, which
-// starts from zero, -2 or -3 - slot); with POOL
+// descendants.  Those live in slots, the last of which (ustride - 1) stays zero and
+// is read by the panel entries that receive no update (su_rows gives every entry's
+// slot); with POOL
 // the slots are a pool in LDS, reused once a panel has consumed them, otherwise
 // a per-candidate array in global memory.  The first update of a slot in block
-// order overwrites it (up_u = slot << 1 | first), so no slot needs clearing.  The
+// order overwrites it (code = slot << 1 | first), so no other slot needs clearing.  The
 // factor is stored (the whole panel, zeros above the diagonal) only by the
 // candidates whose factor is used afterwards: the gamma twins, or the single
-// factorisation when dual is false.
-constexpr int kPairsPer = 4;   // update pairs per lane loaded ahead of the elimination
+// factorisation when dual is false.  The block sizes (wc_meta: w, h, offset) come
+// with the block's other inputs, one block ahead, through vector loads.
 constexpr int kPrLd = 34;      // LDS row stride of L21 (doubles): rows fall on different banks
+typedef double wd4 __attribute__((ext_vector_type(4)));   // one MFMA accumulator
 
-template <bool POOL>
+template <bool POOL, int RT>
 __global__ void __launch_bounds__(64)
-k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
-               const int64_t *__restrict__ bl_off, const int64_t *__restrict__ up_ptr,
-               const int *__restrict__ up_pair, const int *__restrict__ up_u, const int *__restrict__ su_rows,
-               const double2 *__restrict__ yd_rows, bool dual, const double *__restrict__ bracket, int round,
-               int ntest, double gamma, double *__restrict__ Lbase, int64_t stride, double *__restrict__ Ubase,
-               int64_t ustride, int prcap, int *__restrict__ fail) {
+k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__ wc_up,
+               const int *__restrict__ su_rows, const double2 *__restrict__ yd_rows, bool dual,
+               const double *__restrict__ bracket, int round, int ntest, double gamma,
+               double *__restrict__ Lbase, int64_t stride, double *__restrict__ Ubase, int64_t ustride,
+               int prcap, int *__restrict__ fail) {
+    constexpr int MT = RT * (RT + 1) / 2;   // lower tile pairs (ti >= tj), ti-major
     extern __shared__ double sm[];
-    double *Pr = sm;   // rows >= w of the factored panel, kPrLd doubles per row (prcap doubles)
+    double *Pr = sm;            // rows >= w of the factored panel, kPrLd doubles per row (prcap doubles)
+    double *Wl = sm + prcap;    // the elimination's multipliers (64 doubles, 16-byte aligned)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
     // each candidate is one long dependent chain: ahead of the waves of concurrent kernels
@@ -214,68 +222,58 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
     const double al = dual ? cand_alpha(cand, ntest, round, gamma, bracket) : 0.0;
     const bool keep = !dual || cand >= ntest;   // the factor is used afterwards
     double *L = Lbase + cand * stride;
-    double *U = POOL ? sm + prcap : Ubase + cand * ustride;
-    // inputs of the next block (row lane of its 64 x 32 tile, row-major: 32 (y, dy)
-    // pairs and 32 slot codes, forty 16-byte loads), in flight while the current
-    // block is processed
+    double *U = POOL ? sm + prcap + 64 : Ubase + cand * ustride;
+    if (lane == 0) U[ustride - 1] = 0.0;   // the slot of the entries without updates
+    if (!POOL) __threadfence_block();
+    // inputs of the next block, in flight while the current block is processed: the
+    // row lane of its 64 x 32 tile (32 (y, dy) pairs and 32 slot codes; each load
+    // reads one column, or four columns of codes, for all 64 rows), its sizes and its
+    // update codes
     double2 q[32];
     int qsu[32];
+    int qm;
+    int4 qu[MT];
     auto issue = [&](int bb) {
-        const size_t r = (size_t(bb) * 64 + lane) * 32;
-        const int4 *sp = reinterpret_cast<const int4 *>(su_rows + r);
+        const double2 *yp = yd_rows + size_t(bb) * 2048 + lane;
+        const int4 *sp = reinterpret_cast<const int4 *>(su_rows) + size_t(bb) * 512 + lane;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) q[k] = yd_rows[r + k];
+        for (int k = 0; k < 32; ++k) q[k] = yp[64 * k];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int4 t = sp[u];
+            const int4 t = sp[64 * u];
             qsu[4 * u] = t.x;
             qsu[4 * u + 1] = t.y;
             qsu[4 * u + 2] = t.z;
             qsu[4 * u + 3] = t.w;
         }
+        qm = wc_meta[4 * bb + (lane & 3)];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) qu[t] = wc_up[(size_t(bb) * MT + t) * 64 + lane];
     };
     issue(0);
     for (int b = 0; b < nb; ++b) {
-        const int w = bl_first[b + 1] - bl_first[b];
-        const int h = int(bl_rptr[b + 1] - bl_rptr[b]);
-        const int64_t off = bl_off[b];
-        const int64_t p0 = up_ptr[b];
-        const int np = int(up_ptr[b + 1] - p0);
-        int pu[kPairsPer], pp[kPairsPer];
+        const int w = __builtin_amdgcn_readlane(qm, 0);
+        const int h = __builtin_amdgcn_readlane(qm, 1);
+        const int64_t off = __builtin_amdgcn_readlane(qm, 2);
+        const int hp = h - w;
+        int4 up[MT];
 #pragma unroll
-        for (int m = 0; m < kPairsPer; ++m) {
-            const int t = min(lane + 64 * m, max(np - 1, 0));
-            pu[m] = (np > 0) ? up_u[p0 + t] : -1;
-            pp[m] = (np > 0) ? up_pair[p0 + t] : 0;
-            if (lane + 64 * m >= np) pu[m] = -1;
-        }
+        for (int t = 0; t < MT; ++t) up[t] = qu[t];
         // the panel of the candidate: Y + alpha dY plus the pending updates
         double a[32];
         int su[32];
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
-            const int v = qsu[k];   // -2 outside the panel as well
-            a[k] = (v <= -2) ? 0.0 : fma(al, q[k].y, q[k].x);   // padding starts from zero
-            su[k] = (v >= 0) ? v : ((v <= -3) ? -3 - v : -1);
+            a[k] = fma(al, q[k].y, q[k].x);
+            su[k] = qsu[k];
         }
         if (b + 1 < nb) issue(b + 1);
-        // every lane reads a slot (slot 0 where there is none) and discards the unused
-        // values: no divergent branches, all reads in flight together
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            const double pv = U[max(su[k], 0)];
-            a[k] += (su[k] >= 0) ? pv : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            if (k < w) {   // uniform
-                const double d = lane_bcast(a[k], k);
-                const double inv = rsqrt_newton(d);
-                const double l = (lane >= k) ? a[k] * inv : 0.0;   // row k gets sqrt(d)
-                a[k] = l;
-                elim_step_bcast(a, l, k, 0);
-            }
-        }
+        for (int k = 0; k < 32; ++k) a[k] += U[su[k]];
+        // 16 or 32 columns are eliminated: the columns k >= w only collect values that
+        // nothing reads, and never feed the columns below w
+        if (w <= 16) elim_lds<16>(reinterpret_cast<double(&)[16]>(a), 0, Wl);
+        else elim_lds<32>(a, 0, Wl);
         // a pivot that is not positive and finite leaves a NaN (or 0 * inf) on the
         // diagonal: one check per block instead of one per pivot inside the chain
         double dg = 0.0;
@@ -286,39 +284,72 @@ k_sn_chol_wave(int nb, const int *__restrict__ bl_first, const int64_t *__restri
             if (lane == 0) fail[cand] = b + 1;
             return;   // uniform
         }
-        if (keep) {
+        // the elimination left zeros above the diagonal, and rows >= h are zero
+        if (keep && lane < h) {
+            double *p = L + off + lane;
 #pragma unroll
-            for (int k = 0; k < 32; ++k)
-                if (k < w && lane < h) L[off + lane + int64_t(h) * k] = (lane >= k) ? a[k] : 0.0;
+            for (int k = 0; k < 32; ++k) {
+                if (k < w) *p = a[k];   // uniform
+                p += h;
+            }
         }
-        if (lane >= w && lane < h) {
+        // L21 rows, columns >= w as zeros; with two row tiles, the rows up to 31 below
+        // hp as zeros too (the MFMA operands are then read without masks)
+        if (lane >= w && (RT == 2 ? lane < w + 32 : lane < h)) {
+            double2 *pr = reinterpret_cast<double2 *>(Pr + (lane - w) * kPrLd);
+            if (w == 32) {   // uniform
 #pragma unroll
-            for (int k = 0; k < 32; k += 2)
-                *reinterpret_cast<double2 *>(Pr + (lane - w) * kPrLd + k) =
-                    double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
+                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{a[k], a[k + 1]};
+            } else {
+#pragma unroll
+                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
+            }
         }
         // one wave: its own LDS stores only need to have completed, no barrier
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
-        auto dot_rows = [&](int pr) {
-            const double2 *x = reinterpret_cast<const double2 *>(Pr + (pr & 0xffff) * kPrLd);
-            const double2 *y = reinterpret_cast<const double2 *>(Pr + (pr >> 16) * kPrLd);
-            double s0 = 0.0, s1 = 0.0;
+        // MFMA operands: lane l holds L21(16 t + l % 16, 4 s + l / 16), zero below row hp
+        double x[RT][8];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const double2 p = x[u], q = y[u];
-                s0 = fma(p.x, q.x, s0);
-                s1 = fma(p.y, q.y, s1);
+        for (int t = 0; t < RT; ++t) {
+            const int row = 16 * t + (lane & 15);
+            const double *pr = Pr + (RT == 2 ? row : max(min(row, hp - 1), 0)) * kPrLd + (lane >> 4);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const double v = pr[4 * s];
+                x[t][s] = (RT == 2 || row < hp) ? v : 0.0;
             }
-            return s0 + s1;
+        }
+        // element r of tile pair t: L21 L21^T(16 ti + 4 r + l / 16, 16 tj + l % 16)
+        auto apply = [&](const int4 &c, const wd4 &v) {
+            if (c.x >= 0) U[c.x >> 1] = ((c.x & 1) ? 0.0 : U[c.x >> 1]) - v[0];
+            if (c.y >= 0) U[c.y >> 1] = ((c.y & 1) ? 0.0 : U[c.y >> 1]) - v[1];
+            if (c.z >= 0) U[c.z >> 1] = ((c.z & 1) ? 0.0 : U[c.z >> 1]) - v[2];
+            if (c.w >= 0) U[c.w >> 1] = ((c.w & 1) ? 0.0 : U[c.w >> 1]) - v[3];
         };
-        auto apply = [&](int u, int pr) { U[u >> 1] = ((u & 1) ? 0.0 : U[u >> 1]) - dot_rows(pr); };
+        // all tile pairs' chains interleaved; with four row tiles, one row tile's
+        // pairs at a time (registers)
+        constexpr int G = RT <= 2 ? RT : 1;   // row tiles per group
 #pragma unroll
-        for (int m = 0; m < kPairsPer; ++m)
-            if (pu[m] >= 0) apply(pu[m], pp[m]);
-        for (int t = 64 * kPairsPer + lane; t < np; t += 64) {
-            const int u = up_u[p0 + t];
-            if (u >= 0) apply(u, up_pair[p0 + t]);
+        for (int g = 0; g < RT; g += G) {
+            constexpr int NG = G == RT ? MT : RT;   // most pairs in a group
+            wd4 acc[NG];
+#pragma unroll
+            for (int t = 0; t < NG; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                int t = 0;
+#pragma unroll
+                for (int ti = g; ti < g + G; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj <= ti; ++tj, ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ti][s], x[tj][s], acc[t], 0, 0, 0);
+            }
+            int t = 0;
+#pragma unroll
+            for (int ti = g; ti < g + G; ++ti)
+#pragma unroll
+                for (int tj = 0; tj <= ti; ++tj, ++t) apply(up[ti * (ti + 1) / 2 + tj], acc[t]);
         }
         // the next block reads these updates (other lanes' included)
         if (POOL) __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -680,36 +711,41 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 
 }  // namespace
 
-// LDS of the one-wave factorisation: the rows of L21 plus, with a pool, the pool
+// LDS of the one-wave factorisation: the rows of L21, the multipliers and, with a
+// pool, the pool
 static size_t wave_chol_lds(const DevStruct &d) {
-    return sizeof(double) * (size_t(d.max_h) * kPrLd + (d.u_pool ? size_t(d.nU < 1 ? 1 : d.nU) : 0));
+    return wave_chol_lds_bytes(d.max_h, d.u_pool ? d.nU : 0);
 }
 
 static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool dual, const double *bracket,
                              int round, int ntest, double gamma, double *L, int64_t stride, double *U, int *fail,
                              hipStream_t st) {
-    const int prcap = d.max_h * kPrLd;
-    if (d.u_pool)
-        hipLaunchKernelGGL(k_sn_chol_wave<true>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
-                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.su_rows, yd, dual, bracket, round,
-                           ntest, gamma, L, stride, U, d.nU, prcap, fail);
-    else
-        hipLaunchKernelGGL(k_sn_chol_wave<false>, dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.bl_first,
-                           d.bl_rptr, d.bl_off, d.up_ptr, d.up_pair, d.up_u, d.su_rows, yd, dual, bracket, round,
-                           ntest, gamma, L, stride, U, d.nU, prcap, fail);
+    const int prcap = std::max(d.max_h, 32) * kPrLd;
+    const int4 *up = reinterpret_cast<const int4 *>(d.wc_up);
+#define SDPC_WAVE_CHOL(POOL, RT)                                                                                 \
+    hipLaunchKernelGGL((k_sn_chol_wave<POOL, RT>), dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.wc_meta, up, \
+                       d.su_rows, yd, dual, bracket, round, ntest, gamma, L, stride, U, d.nU, prcap, fail)
+    if (d.wc_rt == 2) {
+        if (d.u_pool) SDPC_WAVE_CHOL(true, 2);
+        else SDPC_WAVE_CHOL(false, 2);
+    } else {
+        if (d.u_pool) SDPC_WAVE_CHOL(true, 4);
+        else SDPC_WAVE_CHOL(false, 4);
+    }
+#undef SDPC_WAVE_CHOL
 }
 
 size_t wave_chol_work_doubles(const DevStruct &d) { return size_t(d.nb) * 64 * 32 * 2; }
 
 size_t wave_chol_lds_bytes(int max_h, int64_t npool) {
-    return sizeof(double) * (size_t(max_h) * kPrLd + size_t(npool < 1 ? 1 : npool));
+    return sizeof(double) * (size_t(std::max(max_h, 32)) * kPrLd + 64 + size_t(npool < 1 ? 1 : npool));
 }
 
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,
                     hipStream_t st) {
     if (d.max_h <= 64) {
         double2 *yd = reinterpret_cast<double2 *>(work);
-        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, Y,
+        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, d.wE, Y,
                            (const double *)nullptr, yd);
         launch_wave_chol(d, 1, yd, false, nullptr, 0, 1, 0.0, L, 0, U, fail, st);
         return;
@@ -732,7 +768,8 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
     const size_t lds = size_t(d.max_panel) * sizeof(double);
     double2 *yd = reinterpret_cast<double2 *>(work);
     if (d.max_h <= 64)
-        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, Y, dY, yd);
+        hipLaunchKernelGGL(k_yd_rows, dim3(d.nb), dim3(256), 0, st, d.bl_first, d.bl_rptr, d.bl_off, d.wE, Y, dY,
+                           yd);
     for (int r = 0; r < rounds; ++r) {
         const int nc = dual_step_candidates(r, rounds, ntest);
         if (d.max_h <= 64) {

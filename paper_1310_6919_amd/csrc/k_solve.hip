@@ -983,7 +983,7 @@ size_t solve_lds_mma(const DevStruct &d) {
 }
 
 size_t walk_g_lds(const DevStruct &d) {
-    const size_t nf1 = size_t(std::max(d.nfwd, 1)), nb1 = size_t(std::max(d.nbwd, 1));
+    const size_t nf1 = size_t(std::max(d.wk_nfwd, 1)), nb1 = size_t(std::max(d.wk_nbwd, 1));
     return sizeof(double) * (nf1 + nb1) * kRhs + sizeof(WalkDesc) * size_t(d.nb) + sizeof(int) * (nf1 + (nf1 & 1)) +
            sizeof(double) * 2 * 16 * 33;   // the ring of forward results read by the backward walk
 }
@@ -1012,8 +1012,8 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
     const int nt = (d.n + 31) / 32;
     if (!d.solve_generic && G0 && (nf == 1 || G1) && !Dm0 && !Dm1 && walk_g_ok(d)) {
         hipLaunchKernelGGL(k_walk_g, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), walk_g_lds(d), st, d.n, d.nb,
-                           d.bl_first, d.bl_rptr, d.bl_subfirst, d.wk_fs, d.wk_fb, d.wk_bs, d.col_block, d.nfwd,
-                           d.nbwd, G0, out0, G1, out1);
+                           d.bl_first, d.bl_rptr, d.bl_subfirst, d.wk_fs, d.wk_fb, d.wk_bs, d.col_block,
+                           d.wk_nfwd, d.wk_nbwd, G0, out0, G1, out1);
         hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
         return;
     }

@@ -57,17 +57,23 @@ struct DevStruct {
     const int64_t *up_ptr = nullptr;    // nb + 1: update pairs of each block
     const int *up_pair = nullptr;       // (a | c << 16), a >= c, indices into the non-own rows
     const int *up_slot = nullptr;       // target slot, -1 if not stored (value is exactly zero)
-    // pending updates of the one-wave factorisation live in slots: up_u = (slot << 1) |
-    // (first update of the slot in block order), or -1; slot_u = slot of an E slot that
-    // receives updates, -1 if none; on padding -2, or -3 - slot if it receives updates.  With u_pool the nU slots are a pool
-    // in LDS reused after their panel is consumed; otherwise one slot per target entry,
-    // in global memory, nU per candidate.
-    const int *up_u = nullptr;
-    const int *slot_u = nullptr;        // nslot
+    // pending updates of the one-wave factorisation live in slots: an update's code is
+    // (slot << 1) | (first update of the slot in block order), or -1.  With u_pool the
+    // nU slots are a pool in LDS reused after their panel is consumed; otherwise one
+    // slot per target entry, in global memory, nU per candidate.  The last slot
+    // (nU - 1) stays zero.
     int64_t nU = 0;
     int u_pool = 0;
-    const int *su_rows = nullptr;       // nb x 64 x 32: slot_u of each panel tile, row-major (-2 outside)
-    int nfwd = 0, nbwd = 0;
+    const int *su_rows = nullptr;       // nb x 8 x 64 x 4: the slot each panel entry adds (row i, column k
+                                        // at [k / 4][i][k % 4]; nU - 1 where none and outside)
+    // the one-wave factorisation's per-block sizes (w, h, offset, 0) and, for each of the
+    // wc_rt (wc_rt + 1) / 2 lower tile pairs of L21 L21^T, lane l and element r, the
+    // update code of the entry (16 ti + 4 r + l / 16, 16 tj + l % 16) or -1 (int4 per lane)
+    const int *wc_meta = nullptr;
+    const int *wc_up = nullptr;
+    int wc_rt = 2;
+    int nfwd = 0, nbwd = 0;             // live rows of the multi-right-hand-side substitutions
+    int wk_nfwd = 0, wk_nbwd = 0;       // and of the single-product walks
     const int *col_block = nullptr;     // n: block of every column
     const int *slot_row = nullptr;      // nslot: row position of an E slot, -1 on padding
     const int *slot_col = nullptr;      // nslot: column position of an E slot, -1 on padding

@@ -283,7 +283,7 @@ std::string build_symbolic(int n, const std::vector<int> &arow, const std::vecto
     return "";
 }
 
-SolveSlots build_solve_slots(const Symbolic &S) {
+SolveSlots build_solve_slots(const Symbolic &S, bool delay) {
     SolveSlots R;
     const int n = S.n;
     R.fwd.assign(n, -1);
@@ -304,14 +304,18 @@ SolveSlots build_solve_slots(const Symbolic &S) {
             if (first_touch[i] >= 0) born[first_touch[i]].push_back(i);
         std::priority_queue<int, std::vector<int>, std::greater<int>> freel;
         int used = 0;
+        auto release = [&](int b) {
+            for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j)
+                if (R.fwd[j] >= 0) freel.push(R.fwd[j]);
+        };
         for (int b = 0; b < S.nb; ++b) {
+            if (!delay) release(b);   // free for the rows born at b
             for (int i : born[b]) {
                 int s;
                 if (!freel.empty()) { s = freel.top(); freel.pop(); } else { s = used++; }
                 R.fwd[i] = s;
             }
-            for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j)   // free from block b + 1 on
-                if (R.fwd[j] >= 0) freel.push(R.fwd[j]);
+            if (delay) release(b);   // free from block b + 1 on
         }
         R.nfwd = used;
         R.birth = first_touch;
@@ -325,13 +329,16 @@ SolveSlots build_solve_slots(const Symbolic &S) {
         std::priority_queue<int, std::vector<int>, std::greater<int>> freel;
         int used = 0;
         for (int b = S.nb - 1; b >= 0; --b) {
+            if (!delay)
+                for (int i : dies[b]) freel.push(R.bwd[i]);   // read at b, then reused by b's rows
             for (int j = S.bl_first[b]; j < S.bl_first[b + 1]; ++j) {
                 if (last_read[j] < 0) continue;
                 int s;
                 if (!freel.empty()) { s = freel.top(); freel.pop(); } else { s = used++; }
                 R.bwd[j] = s;
             }
-            for (int i : dies[b]) freel.push(R.bwd[i]);              // read at b, free from b - 1 on
+            if (delay)
+                for (int i : dies[b]) freel.push(R.bwd[i]);   // read at b, free from b - 1 on
         }
         R.nbwd = used;
     }

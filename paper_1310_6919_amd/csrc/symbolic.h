@@ -72,15 +72,16 @@ std::vector<int> min_degree_order(int n, const std::vector<int> &arow,
 // reaches it until its own block; for the backward sweep (blocks descending)
 // from its own block until the last block that reads it.  Intervals are
 // coloured greedily; returns the number of slots used.
-// A slot freed at a block becomes free for rows of the next block on, so no block
-// step reads a slot as one of its own rows while writing it as a row below (or the
-// reverse on the backward walk).
+// With delay set, a slot freed at a block becomes free for rows of the next block on,
+// so no block step reads a slot as one of its own rows while writing it as a row below
+// (or the reverse on the backward walk); without it, a block's own rows give their
+// slots to the rows it brings to life, which needs fewer slots.
 struct SolveSlots {
     int nfwd = 0, nbwd = 0;
     std::vector<int> fwd;             // per row: forward slot, -1 if never updated
     std::vector<int> bwd;             // per row: backward slot, -1 if never read
     std::vector<int> birth;           // per row: first block that updates it, -1 if none
 };
-SolveSlots build_solve_slots(const Symbolic &S);
+SolveSlots build_solve_slots(const Symbolic &S, bool delay);
 
 }  // namespace sdpc
