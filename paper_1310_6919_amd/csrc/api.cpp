@@ -75,7 +75,7 @@ struct sdpc_handle {
     double *Dblk = nullptr;   // factorization 1: D of X^ = L^T D L, w x w per storage block (Lhat holds L^{-1})
     double *Xh = nullptr, *Yi = nullptr, *W = nullptr, *T = nullptr;   // dense n x n, support work
     double *B = nullptr, *g = nullptr, *hcol = nullptr;
-    double *scal = nullptr, *alpha_cl = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
+    double *scal = nullptr, *alpha_cl = nullptr, *alpha_hi = nullptr, *alphas = nullptr, *cand = nullptr, *part = nullptr;
     double *ccwork = nullptr; // blocks of the column-compressed general SCM (cc_work_doubles)
     double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
     double *mwork = nullptr;  // partial results of the metrics
@@ -844,6 +844,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->scal, 16));
     TRY(dalloc(h, &h->mwork, metrics_work_doubles(m)));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
+    TRY(dalloc(h, &h->alpha_hi, size_t(S.ncl)));
     TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
     TRY(dalloc(h, &h->ubuf, std::max<size_t>(size_t(d.nU), 1) * kCand));
@@ -1154,7 +1155,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     TRY(dual_step_launch(h));
     launch_zcol(d, h->Xh, h->dY, h->W, st);
     launch_dX_blocked(d, h->W, h->Yi, h->X, bm, h->part, h->dX, st);
-    launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->scal + 8, st);
+    launch_alpha_cliques(d, h->X, h->dX, h->alpha_cl, h->alpha_hi, h->scal + 8, st);
     // Step 4 for X with alpha_p still on the device, into Xn (X itself is replaced
     // only once the iteration is known to have succeeded), then Algorithm 1 and
     // Lhat's diagonal inverses for the next iteration while the dual step runs

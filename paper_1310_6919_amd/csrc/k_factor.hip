@@ -605,13 +605,25 @@ k_alpha_cl(const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_ma
 // per workgroup) and no barriers: lane i holds row i of the clique block (in the
 // reversed order Algorithm 1 factorises in) and of the direction; each test is a
 // readlane elimination as in k_sn_chol_wave, a pivot that is not positive and
-// finite leaving a NaN on the diagonal.  The bisection is the same.
+// finite leaving a NaN on the diagonal.  The bisection is the same, run in two
+// launches: phase 0 tests 1 and takes the first `steps` halvings of (0, 1),
+// leaving (lo, hi) per clique; phase 1 finishes the bisection only for the cliques
+// whose lo is below the smallest hi (*mhi), the only ones whose result can be the
+// minimum over the cliques; the others keep lo, no smaller than that minimum.  The
+// minimum is the one the whole bisection of every clique gives.
 __global__ void __launch_bounds__(256)
 k_alpha_cl_wave(int ncl, const int64_t *__restrict__ cl_ptr, const int64_t *__restrict__ cl_map_ptr,
                 const int *__restrict__ cl_map, const double *__restrict__ Xbar, const double *__restrict__ dX,
-                double *__restrict__ alpha_cl) {
+                double *__restrict__ alpha_lo, double *__restrict__ alpha_hi, int phase, int steps,
+                const double *__restrict__ mhi) {
     const int r = 4 * int(blockIdx.x) + int(threadIdx.x >> 6);
     if (r >= ncl) return;   // uniform per wave
+    double lo = 0.0, hi = 1.0;
+    if (phase == 1) {
+        lo = alpha_lo[r];
+        hi = alpha_hi[r];
+        if (!(lo < *mhi)) return;   // uniform: not a candidate for the minimum
+    }
     const int lane = threadIdx.x & 63;
     const int c = int(cl_ptr[r + 1] - cl_ptr[r]);
     const int *map = cl_map + cl_map_ptr[r];
@@ -644,19 +656,19 @@ k_alpha_cl_wave(int ncl, const int64_t *__restrict__ cl_ptr, const int64_t *__re
             if (k == lane) dg = a[k];
         return __ballot(lane < c && !((dg > 0.0) && isfinite(dg))) == 0ull;
     };
-    double res;
-    if (test(1.0)) {
-        res = 1.0;
+    if (phase == 0 && test(1.0)) {
+        lo = hi = 1.0;
     } else {
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 52; ++it) {
+        for (int it = 0; it < steps; ++it) {
             const double mid = 0.5 * (lo + hi);
             if (mid <= lo || mid >= hi) break;
             if (test(mid)) lo = mid; else hi = mid;
         }
-        res = lo;
     }
-    if (lane == 0) alpha_cl[r] = res;
+    if (lane == 0) {
+        alpha_lo[r] = lo;
+        alpha_hi[r] = hi;
+    }
 }
 
 // After a round of candidate tests (fail[c] == 0: Y + a_c dY positive definite),
@@ -801,14 +813,20 @@ void launch_ldl_cliques(const DevStruct &d, const double *Xbar, double *Linv, do
 }
 
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX, double *alpha_cl,
-                          double *out, hipStream_t st) {
-    if (d.max_clique <= 32)
+                          double *alpha_hi, double *out, hipStream_t st) {
+    if (d.max_clique <= 32) {
+        // 52 halvings in all: 10 for every clique, the rest for the candidates
+        constexpr int kFirst = 10;
         hipLaunchKernelGGL(k_alpha_cl_wave, dim3((d.ncl + 3) / 4), dim3(256), 0, st, d.ncl, d.cl_ptr, d.cl_map_ptr,
-                           d.cl_map, Xbar, dX, alpha_cl);
-    else
+                           d.cl_map, Xbar, dX, alpha_cl, alpha_hi, 0, kFirst, (const double *)nullptr);
+        hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, (const double *)alpha_hi, out);
+        hipLaunchKernelGGL(k_alpha_cl_wave, dim3((d.ncl + 3) / 4), dim3(256), 0, st, d.ncl, d.cl_ptr, d.cl_map_ptr,
+                           d.cl_map, Xbar, dX, alpha_cl, alpha_hi, 1, 52 - kFirst, (const double *)out);
+    } else {
         hipLaunchKernelGGL(k_alpha_cl, dim3(d.ncl), dim3(256), 0, st, d.cl_ptr, d.cl_map_ptr, d.cl_map, Xbar, dX,
                            alpha_cl);
-    hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, alpha_cl, out);
+    }
+    hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, st, d.ncl, (const double *)alpha_cl, out);
 }
 
 }  // namespace sdpc

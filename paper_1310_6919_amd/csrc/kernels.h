@@ -205,7 +205,7 @@ void launch_ldl_cliques(const DevStruct &d, const double *Xbar, double *Linv, do
                         hipStream_t st);
 // eq. primal_length2: per-clique maximal step, then the minimum into *out
 void launch_alpha_cliques(const DevStruct &d, const double *Xbar, const double *dX,
-                          double *alpha_cl, double *out, hipStream_t st);
+                          double *alpha_cl, double *alpha_hi, double *out, hipStream_t st);
 
 // ---- sparse substitutions (k_solve.hip): out = (L L^T)^{-1}, n x n, full symmetric
 int solve_tile_width(const DevStruct &d);
