@@ -400,15 +400,16 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             }
         }
         // the pool is used when the factorisation's LDS stays within the budget (32 KiB by
-        // default: four waves per compute unit); one more slot stays zero
+        // default: four waves per compute unit); two more slots: one stays zero, one
+        // takes the results that update nothing
         d.u_pool = (h->prm.pool_lds_bytes > 0 &&
-                    wave_chol_lds_bytes(S.max_h, used + 1) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
+                    wave_chol_lds_bytes(S.max_h, used + 2) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
         if (!d.u_pool) {   // one slot per target entry, in global memory
             int k = 0;
             for (int64_t s = 0; s < S.nslot; ++s)
                 if (born_at[s] >= 0) slot_u[s] = k++;
         }
-        d.nU = (d.u_pool ? used : ntarget) + 1;
+        d.nU = (d.u_pool ? used : ntarget) + 2;
         std::vector<uint8_t> seen(size_t(S.nslot), 0);
         for (int b = 0; b < S.nb; ++b)
             for (int64_t t = up_ptr[b]; t < up_ptr[b + 1]; ++t) {
@@ -428,7 +429,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     // order: per group of four columns, per row, the four slots
     std::vector<int> su_rows;
     if (S.max_h <= 64 && S.max_w <= 32) {
-        const int zero = int(d.nU - 1);
+        const int zero = int(d.nU - 2);
         su_rows.assign(size_t(S.nb) * 64 * 32, zero);
         for (int b = 0; b < S.nb; ++b) {
             const int w = S.bl_first[b + 1] - S.bl_first[b];
@@ -460,9 +461,11 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         for (int b = 0; b < S.nb; ++b) {
             const int hp = int(S.bl_rptr[b + 1] - S.bl_rptr[b]) - (S.bl_first[b + 1] - S.bl_first[b]);
             // pair (a, c), a >= c: up_ptr[b] + c hp - c (c - 1) / 2 + (a - c)
+            const int trash = int(d.nU - 1) << 1;
             auto code = [&](int a, int c) {
-                if (a >= hp || c >= hp || a < c) return -1;
-                return up_u[size_t(up_ptr[b] + int64_t(c) * hp - int64_t(c) * (c - 1) / 2 + (a - c))];
+                if (a >= hp || c >= hp || a < c) return trash;
+                const int u = up_u[size_t(up_ptr[b] + int64_t(c) * hp - int64_t(c) * (c - 1) / 2 + (a - c))];
+                return u >= 0 ? u : trash;
             };
             int t = 0;
             for (int ti = 0; ti < rt; ++ti)

@@ -187,9 +187,9 @@ k_yd_rows(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
 // candidate is never written out: a panel is formed when its block is reached,
 // from Y and dY (copied per panel row-major by k_yd_rows, read one block ahead
 // while the previous block is factorised) and the pending updates of its
-// descendants.  Those live in slots, the last of which (ustride - 1) stays zero and
-// is read by the panel entries that receive no update (su_rows gives every entry's
-// slot); with POOL
+// descendants.  Those live in slots; the second last (ustride - 2) stays zero and is
+// read by the panel entries that receive no update (su_rows gives every entry's
+// slot), the last takes the results that update nothing (so every lane writes); with POOL
 // the slots are a pool in LDS, reused once a panel has consumed them, otherwise
 // a per-candidate array in global memory.  The first update of a slot in block
 // order overwrites it (code = slot << 1 | first), so no other slot needs clearing.  The
@@ -209,7 +209,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
                int prcap, int *__restrict__ fail) {
     constexpr int MT = RT * (RT + 1) / 2;   // lower tile pairs (ti >= tj), ti-major
     extern __shared__ double sm[];
-    double *Pr = sm;            // rows >= w of the factored panel, kPrLd doubles per row (prcap doubles)
+    double *Pr = sm;            // the 64 rows of the factored panel, kPrLd doubles per row (prcap doubles)
     double *Wl = sm + prcap;    // the elimination's multipliers (64 doubles, 16-byte aligned)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
@@ -223,7 +223,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
     const bool keep = !dual || cand >= ntest;   // the factor is used afterwards
     double *L = Lbase + cand * stride;
     double *U = POOL ? sm + prcap + 64 : Ubase + cand * ustride;
-    if (lane == 0) U[ustride - 1] = 0.0;   // the slot of the entries without updates
+    if (lane == 0) U[ustride - 2] = 0.0;   // the slot of the entries without updates
     if (!POOL) __threadfence_block();
     // inputs of the next block, in flight while the current block is processed: the
     // row lane of its 64 x 32 tile (32 (y, dy) pairs and 32 slot codes; each load
@@ -274,12 +274,21 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
         // nothing reads, and never feed the columns below w
         if (w <= 16) elim_lds<16>(reinterpret_cast<double(&)[16]>(a), 0, Wl);
         else elim_lds<32>(a, 0, Wl);
+        // every row to LDS, columns >= w as zeros (rows >= h are zero): the diagonal for
+        // the check below and, from row w on, the MFMA operands
+        {
+            double2 *pr = reinterpret_cast<double2 *>(Pr + lane * kPrLd);
+            if (w == 32) {   // uniform
+#pragma unroll
+                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{a[k], a[k + 1]};
+            } else {
+#pragma unroll
+                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
+            }
+        }
         // a pivot that is not positive and finite leaves a NaN (or 0 * inf) on the
         // diagonal: one check per block instead of one per pivot inside the chain
-        double dg = 0.0;
-#pragma unroll
-        for (int k = 0; k < 32; ++k)
-            if (k == lane) dg = a[k];
+        const double dg = Pr[min(lane, 31) * (kPrLd + 1)];
         if (__ballot(lane < w && !((dg > 0.0) && isfinite(dg))) != 0ull) {
             if (lane == 0) fail[cand] = b + 1;
             return;   // uniform
@@ -293,27 +302,13 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
                 p += h;
             }
         }
-        // L21 rows, columns >= w as zeros; with two row tiles, the rows up to 31 below
-        // hp as zeros too (the MFMA operands are then read without masks)
-        if (lane >= w && (RT == 2 ? lane < w + 32 : lane < h)) {
-            double2 *pr = reinterpret_cast<double2 *>(Pr + (lane - w) * kPrLd);
-            if (w == 32) {   // uniform
-#pragma unroll
-                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{a[k], a[k + 1]};
-            } else {
-#pragma unroll
-                for (int k = 0; k < 32; k += 2) pr[k / 2] = double2{k < w ? a[k] : 0.0, k + 1 < w ? a[k + 1] : 0.0};
-            }
-        }
-        // one wave: its own LDS stores only need to have completed, no barrier
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        __builtin_amdgcn_wave_barrier();
         // MFMA operands: lane l holds L21(16 t + l % 16, 4 s + l / 16), zero below row hp
+        // (with two row tiles the rows read are below 64 and zero beyond h)
         double x[RT][8];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int row = 16 * t + (lane & 15);
-            const double *pr = Pr + (RT == 2 ? row : max(min(row, hp - 1), 0)) * kPrLd + (lane >> 4);
+            const double *pr = Pr + (w + (RT == 2 ? row : max(min(row, hp - 1), 0))) * kPrLd + (lane >> 4);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 const double v = pr[4 * s];
@@ -322,10 +317,10 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
         }
         // element r of tile pair t: L21 L21^T(16 ti + 4 r + l / 16, 16 tj + l % 16)
         auto apply = [&](const int4 &c, const wd4 &v) {
-            if (c.x >= 0) U[c.x >> 1] = ((c.x & 1) ? 0.0 : U[c.x >> 1]) - v[0];
-            if (c.y >= 0) U[c.y >> 1] = ((c.y & 1) ? 0.0 : U[c.y >> 1]) - v[1];
-            if (c.z >= 0) U[c.z >> 1] = ((c.z & 1) ? 0.0 : U[c.z >> 1]) - v[2];
-            if (c.w >= 0) U[c.w >> 1] = ((c.w & 1) ? 0.0 : U[c.w >> 1]) - v[3];
+            U[c.x >> 1] = ((c.x & 1) ? 0.0 : U[c.x >> 1]) - v[0];
+            U[c.y >> 1] = ((c.y & 1) ? 0.0 : U[c.y >> 1]) - v[1];
+            U[c.z >> 1] = ((c.z & 1) ? 0.0 : U[c.z >> 1]) - v[2];
+            U[c.w >> 1] = ((c.w & 1) ? 0.0 : U[c.w >> 1]) - v[3];
         };
         // all tile pairs' chains interleaved; with four row tiles, one row tile's
         // pairs at a time (registers)
@@ -732,7 +727,7 @@ static size_t wave_chol_lds(const DevStruct &d) {
 static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool dual, const double *bracket,
                              int round, int ntest, double gamma, double *L, int64_t stride, double *U, int *fail,
                              hipStream_t st) {
-    const int prcap = std::max(d.max_h, 32) * kPrLd;
+    const int prcap = 64 * kPrLd;
     const int4 *up = reinterpret_cast<const int4 *>(d.wc_up);
 #define SDPC_WAVE_CHOL(POOL, RT)                                                                                 \
     hipLaunchKernelGGL((k_sn_chol_wave<POOL, RT>), dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.wc_meta, up, \
@@ -750,7 +745,8 @@ static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool
 size_t wave_chol_work_doubles(const DevStruct &d) { return size_t(d.nb) * 64 * 32 * 2; }
 
 size_t wave_chol_lds_bytes(int max_h, int64_t npool) {
-    return sizeof(double) * (size_t(std::max(max_h, 32)) * kPrLd + 64 + size_t(npool < 1 ? 1 : npool));
+    (void)max_h;   // every panel row is staged, 64 of them
+    return sizeof(double) * (size_t(64) * kPrLd + 64 + size_t(npool < 1 ? 1 : npool));
 }
 
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,

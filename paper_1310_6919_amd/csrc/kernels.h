@@ -60,15 +60,16 @@ struct DevStruct {
     // pending updates of the one-wave factorisation live in slots: an update's code is
     // (slot << 1) | (first update of the slot in block order), or -1.  With u_pool the
     // nU slots are a pool in LDS reused after their panel is consumed; otherwise one
-    // slot per target entry, in global memory, nU per candidate.  The last slot
-    // (nU - 1) stays zero.
+    // slot per target entry, in global memory, nU per candidate.  Slot nU - 2 stays
+    // zero, slot nU - 1 takes the results that update nothing.
     int64_t nU = 0;
     int u_pool = 0;
     const int *su_rows = nullptr;       // nb x 8 x 64 x 4: the slot each panel entry adds (row i, column k
-                                        // at [k / 4][i][k % 4]; nU - 1 where none and outside)
+                                        // at [k / 4][i][k % 4]; nU - 2 where none and outside)
     // the one-wave factorisation's per-block sizes (w, h, offset, 0) and, for each of the
     // wc_rt (wc_rt + 1) / 2 lower tile pairs of L21 L21^T, lane l and element r, the
-    // update code of the entry (16 ti + 4 r + l / 16, 16 tj + l % 16) or -1 (int4 per lane)
+    // update code of the entry (16 ti + 4 r + l / 16, 16 tj + l % 16), or that of slot
+    // nU - 1 (int4 per lane)
     const int *wc_meta = nullptr;
     const int *wc_up = nullptr;
     int wc_rt = 2;
