@@ -403,7 +403,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         // default: four waves per compute unit); two more slots: one stays zero, one
         // takes the results that update nothing
         d.u_pool = (h->prm.pool_lds_bytes > 0 &&
-                    wave_chol_lds_bytes(S.max_h, used + 2) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
+                    wave_chol_lds_bytes(S.max_h, S.max_w, used + 2) <= size_t(h->prm.pool_lds_bytes)) ? 1 : 0;
         if (!d.u_pool) {   // one slot per target entry, in global memory
             int k = 0;
             for (int64_t s = 0; s < S.nslot; ++s)

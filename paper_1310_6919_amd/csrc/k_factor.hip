@@ -209,7 +209,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
                int prcap, int *__restrict__ fail) {
     constexpr int MT = RT * (RT + 1) / 2;   // lower tile pairs (ti >= tj), ti-major
     extern __shared__ double sm[];
-    double *Pr = sm;            // the 64 rows of the factored panel, kPrLd doubles per row (prcap doubles)
+    double *Pr = sm;            // rows of the factored panel, kPrLd doubles per row (prcap doubles)
     double *Wl = sm + prcap;    // the elimination's multipliers (64 doubles, 16-byte aligned)
     const int lane = threadIdx.x;
     const int cand = blockIdx.x;
@@ -275,8 +275,9 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
         if (w <= 16) elim_lds<16>(reinterpret_cast<double(&)[16]>(a), 0, Wl);
         else elim_lds<32>(a, 0, Wl);
         // every row to LDS, columns >= w as zeros (rows >= h are zero): the diagonal for
-        // the check below and, from row w on, the MFMA operands
-        {
+        // the check below and, from row w on, the MFMA operands (prcap holds the rows up
+        // to the largest h and w + 31)
+        if (lane * kPrLd < prcap) {
             double2 *pr = reinterpret_cast<double2 *>(Pr + lane * kPrLd);
             if (w == 32) {   // uniform
 #pragma unroll
@@ -721,13 +722,13 @@ __global__ void __launch_bounds__(1024) k_min_reduce(int len, const double *__re
 // LDS of the one-wave factorisation: the rows of L21, the multipliers and, with a
 // pool, the pool
 static size_t wave_chol_lds(const DevStruct &d) {
-    return wave_chol_lds_bytes(d.max_h, d.u_pool ? d.nU : 0);
+    return wave_chol_lds_bytes(d.max_h, d.max_w, d.u_pool ? d.nU : 0);
 }
 
 static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool dual, const double *bracket,
                              int round, int ntest, double gamma, double *L, int64_t stride, double *U, int *fail,
                              hipStream_t st) {
-    const int prcap = 64 * kPrLd;
+    const int prcap = wave_chol_rows(d.max_h, d.max_w) * kPrLd;
     const int4 *up = reinterpret_cast<const int4 *>(d.wc_up);
 #define SDPC_WAVE_CHOL(POOL, RT)                                                                                 \
     hipLaunchKernelGGL((k_sn_chol_wave<POOL, RT>), dim3(nc), dim3(64), wave_chol_lds(d), st, d.nb, d.wc_meta, up, \
@@ -744,9 +745,10 @@ static void launch_wave_chol(const DevStruct &d, int nc, const double2 *yd, bool
 
 size_t wave_chol_work_doubles(const DevStruct &d) { return size_t(d.nb) * 64 * 32 * 2; }
 
-size_t wave_chol_lds_bytes(int max_h, int64_t npool) {
-    (void)max_h;   // every panel row is staged, 64 of them
-    return sizeof(double) * (size_t(64) * kPrLd + 64 + size_t(npool < 1 ? 1 : npool));
+int wave_chol_rows(int max_h, int max_w) { return std::min(64, std::max(max_h, max_w + 32)); }
+
+size_t wave_chol_lds_bytes(int max_h, int max_w, int64_t npool) {
+    return sizeof(double) * (size_t(wave_chol_rows(max_h, max_w)) * kPrLd + 64 + size_t(npool < 1 ? 1 : npool));
 }
 
 void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, double *work, int *fail,

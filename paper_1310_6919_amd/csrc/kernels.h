@@ -176,7 +176,9 @@ void launch_sn_chol(const DevStruct &d, const double *Y, double *L, double *U, d
 // work (doubles) of launch_sn_chol and launch_dual_step; LDS of their one-wave
 // factorisation with a pool of npool update slots
 size_t wave_chol_work_doubles(const DevStruct &d);
-size_t wave_chol_lds_bytes(int max_h, int64_t npool);
+// rows of the one-wave factorisation's LDS panel, and its LDS bytes with a pool of npool slots
+int wave_chol_rows(int max_h, int max_w);
+size_t wave_chol_lds_bytes(int max_h, int max_w, int64_t npool);
 // largest alpha in (0, 1] with Y + alpha dY positive definite: 'rounds' rounds of
 // parallel factorisations of ntest[r] test points (log grid, then even grids inside
 // the bracket), with gamma twins in the last round; the result is bracket[0] (a lower bound;
