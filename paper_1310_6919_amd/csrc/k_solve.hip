@@ -785,12 +785,16 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
     };
     const int b0 = col_block[k0];
     int b = active(b0) ? b0 : next_active(b0);
-    Fwd cur, nxt;
-    if (b < nb) fetch_fwd(b, cur);
-    while (b < nb) {
+    int b1 = b < nb ? next_active(b) : nb;
+    // operands two blocks ahead: a ring of three register sets, the loads of a block in
+    // flight for two steps
+    Fwd fa, fb, fc;
+    if (b < nb) fetch_fwd(b, fa);
+    if (b1 < nb) fetch_fwd(b1, fb);
+    auto fstep = [&](const Fwd &cur, Fwd &pre) {
         const int F = desc[b].F, w = desc[b].w, h = desc[b].h;
-        const int bn = next_active(b);
-        fetch_fwd(bn < nb ? bn : b, nxt);   // in flight during this step
+        const int b2 = b1 < nb ? next_active(b1) : nb;
+        fetch_fwd(b2 < nb ? b2 : b, pre);   // in flight during this step and the next
         // v: the pending updates of the block's own rows plus e_k
         double v[8];
 #pragma unroll
@@ -830,8 +834,16 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
                 if (os[r] >= 0) lwb[os[r]] = b;
         }
         __syncthreads();
-        cur = nxt;
-        b = bn;
+        b = b1;
+        b1 = b2;
+    };
+    for (;;) {
+        if (b >= nb) break;
+        fstep(fa, fc);
+        if (b >= nb) break;
+        fstep(fb, fa);
+        if (b >= nb) break;
+        fstep(fc, fb);
     }
     // the forward results in `out`, stored by other threads, are read below
     __syncthreads();
@@ -891,9 +903,11 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
     };
     double zs0[4], zs1[4];   // loader register sets: block q in set q & 1
     b = nb - 1;
-    Bwd bc, bx;
+    // operands two blocks ahead, as in the forward walk
+    Bwd xa, xb, xc;
     if (wv < 2) {
-        fetch_bwd(b, bc);
+        fetch_bwd(b, xa);
+        if (b - 1 >= b0) fetch_bwd(b - 1, xb);
     } else {
         if (b & 1) zload(b, zs1); else zload(b, zs0);
         if (b - 1 >= b0) {
@@ -905,10 +919,10 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
         }
     }
     __syncthreads();
-    for (; b >= b0; --b) {
+    auto bstep = [&](const Bwd &bc, Bwd &pre) {
         const int F = desc[b].F, w = desc[b].w;
         if (wv < 2) {
-            fetch_bwd(b > b0 ? b - 1 : b, bx);
+            fetch_bwd(b - 2 >= b0 ? b - 2 : b, pre);   // in flight during this step and the next
             if (16 * wv < w) {   // uniform
                 const double *zslot = zr + (b & 1) * (16 * ZLD);
                 d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
@@ -947,7 +961,15 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
             }
         }
         __syncthreads();
-        if (wv < 2) bc = bx;
+        --b;
+    };
+    for (;;) {
+        if (b < b0) break;
+        bstep(xa, xc);
+        if (b < b0) break;
+        bstep(xb, xa);
+        if (b < b0) break;
+        bstep(xc, xb);
     }
 }
 
