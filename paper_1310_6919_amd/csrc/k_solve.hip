@@ -807,13 +807,14 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
             v[ks] = (have ? x : 0.0) + ((k < w && F + k == k0 + li) ? 1.0 : 0.0);
         }
         if (16 * wv < h) {   // uniform
-            d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+            // four independent chains; k-steps beyond the block's columns add nothing
+            d4 a[4];
 #pragma unroll
-            for (int ks = 0; ks < 8; ks += 2) {
-                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks], v[ks], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks + 1], v[ks + 1], a1, 0, 0, 0);
-            }
-            const d4 acc = a0 + a1;
+            for (int t = 0; t < 4; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+                if (4 * ks < w) a[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks], v[ks], a[ks & 3], 0, 0, 0);
+            const d4 acc = (a[0] + a[1]) + (a[2] + a[3]);
             // element r: row 16 wv + 4 r + lq of G v, right-hand side li; every lane of a
             // row reads the row's slot stamp before any of them rewrites it
             int os[4];
@@ -920,27 +921,27 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
     }
     __syncthreads();
     auto bstep = [&](const Bwd &bc, Bwd &pre) {
-        const int F = desc[b].F, w = desc[b].w;
+        const int F = desc[b].F, w = desc[b].w, h = desc[b].h;
         if (wv < 2) {
             fetch_bwd(b - 2 >= b0 ? b - 2 : b, pre);   // in flight during this step and the next
             if (16 * wv < w) {   // uniform
                 const double *zslot = zr + (b & 1) * (16 * ZLD);
-                d4 a0 = d4{0.0, 0.0, 0.0, 0.0}, a1 = a0;
+                // four independent chains; k-steps beyond the block's rows add nothing
+                d4 a[4];
 #pragma unroll
-                for (int ks = 0; ks < 16; ks += 2) {
-                    double u[2];
+                for (int t = 0; t < 4; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const int kk = ks + t, k = 4 * kk + lq;
+                for (int kk = 0; kk < 16; ++kk) {
+                    if (4 * kk < h) {   // uniform
+                        const int k = 4 * kk + lq;
                         const int sv = (k >= w) ? bc.us[kk] : -1;   // -1 beyond the block already
                         const double x = accb[max(sv, 0) * T + li];
                         const double zz = (kk < 8) ? zslot[li * ZLD + (kk < 8 ? k : 0)] : 0.0;
-                        u[t] = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
+                        const double u = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
+                        a[kk & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[kk], u, a[kk & 3], 0, 0, 0);
                     }
-                    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[ks], u[0], a0, 0, 0, 0);
-                    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[ks + 1], u[1], a1, 0, 0, 0);
                 }
-                const d4 acc = a0 + a1;
+                const d4 acc = (a[0] + a[1]) + (a[2] + a[3]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int orow = 16 * wv + 4 * r + lq;
