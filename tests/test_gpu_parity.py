@@ -308,6 +308,52 @@ def test_update_slots_in_memory_match_pool(name):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("bw", [16, 24])
+@pytest.mark.parametrize("pool", [32 * 1024, 0])
+def test_tall_trailing_updates_match_oracle(bw, pool):
+    """Bandwidth 40 in storage blocks of 16 or 24 columns: every panel has up to 40 rows
+    below its diagonal block, so the one-wave factorisation updates the ancestors with
+    four 16-row tiles of L21 (ten tile pairs), and 16-column blocks take the 16-wide
+    elimination; with pool = 0 the pending updates live in device memory.  One SCM
+    evaluation (N, B) and one iteration (direction, both step lengths, the dual step's
+    candidates) against the oracle."""
+    prob = sdpgen.maxcut_band(200, 40, 0.9, 6)
+    from paper_1310_6919_amd.sdpc import sdpc_analyze
+    info = sdpc_analyze(prob, block_width=bw)[0]
+    # some block has more than 32 rows below its own columns, and every block fits a wave
+    assert info["max_block_rows"] - bw > 32 and info["max_block_rows"] <= 64
+    rng = np.random.default_rng(17)
+    Xfull, Y = _state(prob, rng)
+    h = _create(prob, block_width=bw, pool_lds_bytes=pool)
+    B = h.sdpc_scm(dev(to_E(h, Xfull)), dev(to_E(h, Y)))
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    E = ch.E_mask()
+    Xh = oracle.maxdet_complete(ch, np.where(E, Xfull, 0.0))
+    Bref = oracle.dense_scm(oracle.scm.problem_mats(prob), Xh, np.linalg.inv(Y))
+    assert rel_err(np.tril(host(B)), np.tril(Bref)) <= 1e-10
+    N, _ = h.sdpc_get_factors()
+    iE, jE, perm = h.sdpc_get_pattern()
+    pos = np.empty(prob.n, dtype=int)
+    pos[perm] = np.arange(prob.n)
+    ok = iE >= 0
+    Nref = np.linalg.cholesky(Y[np.ix_(perm, perm)])
+    pi, pj = pos[iE[ok]], pos[jE[ok]]
+    assert rel_err(host(N)[ok], Nref[np.maximum(pi, pj), np.minimum(pi, pj)]) <= 1e-11
+    z = rng.standard_normal(prob.m) * 0.1
+    h.sdpc_set_state(dev(to_E(h, Xfull)), dev(to_E(h, Y)), dev(z))
+    h.sdpc_step()
+    dz, dX, dY, (ap, ad) = h.sdpc_get_direction()
+    A = oracle.pdipm.permuted_mats(prob, ch)
+    ref = oracle.mc_direction(ch, A, prob.b, np.where(E, Xfull, 0.0), Y, z)
+    assert rel_err(host(dz), ref["dz"]) <= 1e-9
+    assert rel_err(from_E(h, host(dY)), ref["dY"]) <= 1e-9
+    assert rel_err(from_E(h, host(dX)), ref["dX"]) <= 1e-9
+    assert abs(ap - ref["alpha_p"]) <= 1e-9 * max(1.0, ref["alpha_p"])
+    assert ref["alpha_d"] * (1 - 1e-4) <= ad <= ref["alpha_d"] * (1 + 1e-12)
+    h.close()
+
+
 def test_solve_one_column_blocks_match_wide_blocks():
     """Storage blocks of one column (3000 of them) leave the block walk of the
     inverse-by-solves kernel without room for its descriptor table in LDS, so it
