@@ -827,7 +827,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->hcol, size_t(m)));
     TRY(dalloc(h, &h->DinvN, size_t(dinv_off.back())));
     TRY(dalloc(h, &h->DinvL, size_t(dinv_off.back())));
-    if (walk_g_ok(d) && h->prm.factorization == 0) {
+    if (walk_g_ok(d)) {
         TRY(dalloc(h, &h->GN, size_t(d.nb) * 4096));
         TRY(dalloc(h, &h->GL, size_t(d.nb) * 4096));
     }
@@ -1011,7 +1011,7 @@ void launch_xside(sdpc_handle *h, const double *Xbar, int *fail_clique, int *fai
         launch_ldl_cliques(h->d, Xbar, h->Lhat, h->Dblk, fail_clique, h->st);
     else
         launch_algorithm1(h->d, Xbar, h->Lhat, fail_clique, h->st);
-    launch_dinv(h->d, h->Lhat, h->DinvL, fail_dinv, h->st, h->GL);
+    launch_dinv(h->d, h->Lhat, h->DinvL, fail_dinv, h->st, h->GL, h->Dblk);
 }
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.

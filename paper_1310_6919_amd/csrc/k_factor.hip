@@ -358,7 +358,7 @@ k_sn_chol_wave(int nb, const int *__restrict__ wc_meta, const int4 *__restrict__
 __global__ void __launch_bounds__(64)
 k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, const int64_t *__restrict__ bl_off,
        const int64_t *__restrict__ bl_dinv, const double *__restrict__ L, double *__restrict__ Dinv,
-       int *__restrict__ fail, double *__restrict__ G) {
+       int *__restrict__ fail, double *__restrict__ G, const double *__restrict__ Dm) {
     __shared__ double D[64 * 64];
     const int b = blockIdx.x;
     const int F = bl_first[b];
@@ -392,6 +392,7 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
         // then stored in the walks' lane order, zero outside the block:
         //   forward  (wave f < 4, lane l, ks < 8):  G(16 f + l % 16, 4 ks + l / 16)
         //   backward (wave f < 2, lane l, ks < 16): G(4 ks + l / 16, 16 f + l % 16)
+        // With Dm the forward operand's top block is Dm_b D^{-1} (in LDS where P21 was).
         __syncthreads();
         double *Xs = D, *Ps = D + w * w, *Gs = D + 2048;
         const int hw = h - w;
@@ -410,11 +411,22 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
             Gs[r + h * c] = acc;
         }
         __syncthreads();
+        double *Ts = Ps;   // w x w, after P21 is no longer read (w w <= 2048 - w w)
+        if (Dm) {
+            const double *Db = Dm + bl_dinv[b];
+            for (int i = threadIdx.x; i < w * w; i += blockDim.x) {
+                const int r = i % w, c = i / w;
+                double acc = 0.0;
+                for (int j = c; j < w; ++j) acc = fma(Db[r + w * j], Xs[j + w * c], acc);
+                Ts[i] = acc;
+            }
+            __syncthreads();
+        }
         double *Gb = G + size_t(b) * 4096;
         for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
             const int ks = i % 8, l = (i / 8) % 64, f = i / 512;
             const int r = 16 * f + l % 16, c = 4 * ks + l / 16;
-            Gb[i] = (r < h && c < w) ? Gs[r + h * c] : 0.0;
+            Gb[i] = (r < h && c < w) ? ((Dm && r < w) ? Ts[r + w * c] : Gs[r + h * c]) : 0.0;
         }
         for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
             const int ks = i % 16, l = (i / 16) % 64, f = i / 1024;
@@ -794,9 +806,10 @@ void launch_dual_step(const DevStruct &d, const double *Y, const double *dY, int
     }
 }
 
-void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st, double *G) {
+void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st, double *G,
+                 const double *Dm) {
     hipLaunchKernelGGL(k_dinv, dim3(d.nb), dim3(64), 0, st, d.bl_first, d.bl_rptr, d.bl_off, d.bl_dinv, L,
-                       Dinv, fail, G);
+                       Dinv, fail, G, Dm);
 }
 
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail, hipStream_t st) {

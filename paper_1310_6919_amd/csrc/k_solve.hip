@@ -1033,7 +1033,7 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
                               const double *Dm0, const double *Dm1, const double *G0, const double *G1) {
     const int nf = L1 ? 2 : 1;
     const int nt = (d.n + 31) / 32;
-    if (!d.solve_generic && G0 && (nf == 1 || G1) && !Dm0 && !Dm1 && walk_g_ok(d)) {
+    if (!d.solve_generic && G0 && (nf == 1 || G1) && walk_g_ok(d)) {   // any Dm is inside G
         hipLaunchKernelGGL(k_walk_g, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), walk_g_lds(d), st, d.n, d.nb,
                            d.bl_first, d.bl_rptr, d.bl_subfirst, d.wk_fs, d.wk_fb, d.wk_bs, d.col_block,
                            d.wk_nfwd, d.wk_nbwd, G0, out0, G1, out1);

@@ -193,9 +193,11 @@ int dual_step_candidates(int round, int rounds, const int *ntest);
 // Dinv_b = L_bb^{-1} per storage block (w x w at bl_dinv); with G != nullptr also
 // G_b = [L_bb^{-1}; P21_b L_bb^{-1}] (h x w), the one matrix of a block step of the
 // single-product substitution walks, at G + 4096 b in the walks' lane order
-// (walk_g_layout); needs w <= 32 and h <= 64
+// (walk_g_layout); needs w <= 32 and h <= 64.  With Dm (w x w blocks at bl_dinv)
+// the forward operand's top block is Dm_b L_bb^{-1} instead, so the walks give
+// L^{-T} Dm L^{-1} (the backward operand keeps L_bb^{-1})
 void launch_dinv(const DevStruct &d, const double *L, double *Dinv, int *fail, hipStream_t st,
-                 double *G = nullptr);
+                 double *G = nullptr, const double *Dm = nullptr);
 // Algorithm 1: Lhat from Xbar clique by clique; fail = 1 + clique on a non-PD block
 void launch_algorithm1(const DevStruct &d, const double *Xbar, double *Lhat, int *fail,
                        hipStream_t st);
@@ -216,8 +218,9 @@ int solve_tile_width(const DevStruct &d);
 // with Dm_f != nullptr (w x w blocks at bl_dinv, block diagonal over the supernodes)
 // out_f = L_f^{-T} Dm_f L_f^{-1} instead: with L_f^{-1} of eq. sparse_fact as the
 // factor this is X^ = L^T D L
-// With G0 (and G1 for a second factor) from launch_dinv, no Dm and every block at
-// most 32 wide and 64 high, the walks take one product per block step (walk_g_ok).
+// With G0 (and G1 for a second factor) from launch_dinv (given the same Dm) and every
+// block at most 32 wide and 64 high, the walks take one product per block step
+// (walk_g_ok); Dm then rides in G.
 void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double *Dinv0, double *out0,
                               const double *L1, const double *Dinv1, double *out1, hipStream_t st,
                               const double *Dm0 = nullptr, const double *Dm1 = nullptr,
