@@ -713,7 +713,9 @@ struct WalkDesc {
 constexpr int kWalkWmax = 32, kWalkHmax = 64;
 typedef int i4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kThreads)
+// two workgroups per compute unit (at most 256 registers per lane): at n = 12000 the
+// 1500 tiles of both factors need the second slot
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
          const int *__restrict__ bl_subfirst, const int *__restrict__ wk_fs, const int *__restrict__ wk_fb,
          const int *__restrict__ wk_bs, const int *__restrict__ col_block, int nfwd, int nbwd,
@@ -807,14 +809,14 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
             v[ks] = (have ? x : 0.0) + ((k < w && F + k == k0 + li) ? 1.0 : 0.0);
         }
         if (16 * wv < h) {   // uniform
-            // four independent chains; k-steps beyond the block's columns add nothing
-            d4 a[4];
+            // two independent chains; k-steps beyond the block's columns add nothing
+            d4 a[2];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < 2; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks)
-                if (4 * ks < w) a[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks], v[ks], a[ks & 3], 0, 0, 0);
-            const d4 acc = (a[0] + a[1]) + (a[2] + a[3]);
+                if (4 * ks < w) a[ks & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.g[ks], v[ks], a[ks & 1], 0, 0, 0);
+            const d4 acc = a[0] + a[1];
             // element r: row 16 wv + 4 r + lq of G v, right-hand side li; every lane of a
             // row reads the row's slot stamp before any of them rewrites it
             int os[4];
@@ -926,10 +928,10 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
             fetch_bwd(b - 2 >= b0 ? b - 2 : b, pre);   // in flight during this step and the next
             if (16 * wv < w) {   // uniform
                 const double *zslot = zr + (b & 1) * (16 * ZLD);
-                // four independent chains; k-steps beyond the block's rows add nothing
-                d4 a[4];
+                // two independent chains; k-steps beyond the block's rows add nothing
+                d4 a[2];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
+                for (int t = 0; t < 2; ++t) a[t] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int kk = 0; kk < 16; ++kk) {
                     if (4 * kk < h) {   // uniform
@@ -938,10 +940,10 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
                         const double x = accb[max(sv, 0) * T + li];
                         const double zz = (kk < 8) ? zslot[li * ZLD + (kk < 8 ? k : 0)] : 0.0;
                         const double u = (k < w) ? zz : (sv >= 0 ? -x : 0.0);
-                        a[kk & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[kk], u, a[kk & 3], 0, 0, 0);
+                        a[kk & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(bc.ga[kk], u, a[kk & 1], 0, 0, 0);
                     }
                 }
-                const d4 acc = (a[0] + a[1]) + (a[2] + a[3]);
+                const d4 acc = a[0] + a[1];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int orow = 16 * wv + 4 * r + lq;
