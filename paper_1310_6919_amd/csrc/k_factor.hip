@@ -8,8 +8,12 @@
 //                 Y + alpha_c dY, which turns the same kernel into a parallel
 //                 positive-definiteness test for the dual step length
 //                 (Section 2.2, Step 3).
+//  k_sn_chol_wave the same for panels of at most 64 rows, one wave per
+//                 candidate: rows in registers, the ancestors' update on the
+//                 FP64 MFMA.
 //  k_dinv         inverses of the diagonal blocks of a factor (used by the
-//                 multi-right-hand-side substitutions).
+//                 multi-right-hand-side substitutions) and, for the
+//                 single-product walks, each block's G = [D^{-1}; P21 D^{-1}].
 //  k_algorithm1   Algorithm 1: per clique C_r, the lower Cholesky factor of
 //                 (Xbar(C_r, C_r))^{-1} without forming the inverse: the block
 //                 in reversed order P_r Xbar P_r^T = M_r M_r^T gives it as

@@ -16,17 +16,19 @@
 //             substitution restricted to those rows is self-contained; values
 //             still read by lower blocks stay in LDS slots.
 // The diagonal blocks are applied through their explicit inverses, so each
-// block step is two small dense products.  Panels and inverses are double
-// buffered in LDS: the next block's are loaded into registers while the current
-// block is processed, so a walk pays one memory latency at its start instead of
-// one per block.  Finally the lower triangle is mirrored to make the output
-// symmetric.
+// block step is two small dense products (k_inv_solve_mma, k_inv_solve), or
+// one product with the block's G = [D^{-1}; P21 D^{-1}] (k_walk_g, blocks at
+// most 32 wide and 64 high).  The next block's operands are loaded while the
+// current block is processed, so a walk pays one memory latency at its start
+// instead of one per block.  Finally the lower triangle is mirrored to make the
+// output symmetric.
 //
 // The earlier factorisation X^ = L^T D L (Section 2.1, eq. sparse_fact) runs
 // through the same walks with the sparse unit-lower L^{-1} as the factor: the
 // forward walk gives L e_k, the block-diagonal D (w x w per storage block,
 // zero between supernodes) multiplies each block's part of it before it is
-// stored, and the backward walk applies L^T.
+// stored (in k_walk_g through the top block of the forward operand), and the
+// backward walk applies L^T.
 #include <algorithm>
 
 #include "kernels.h"
