@@ -79,7 +79,7 @@ struct sdpc_handle {
     double *ccwork = nullptr; // blocks of the column-compressed general SCM (cc_work_doubles)
     double *ubuf = nullptr;   // pending updates of the one-wave factorisations, d.nU per candidate
     double *mwork = nullptr;  // partial results of the metrics
-    double *ydw = nullptr, *ydw_dual = nullptr;   // row-major (Y, dY) tiles of the Y factor / dual step
+    double *ydw = nullptr, *ydw_dual = nullptr;   // (Y, dY) panel tiles of the Y factor / dual step
     int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
                             // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
     int64_t ldb = 0;

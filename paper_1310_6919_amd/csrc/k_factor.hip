@@ -189,7 +189,7 @@ k_yd_rows(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr,
 // the diagonal, outside the structure, padding rows).
 // blockIdx.x selects the candidate Y + alpha_c dY (dual == false: Y itself).  The
 // candidate is never written out: a panel is formed when its block is reached,
-// from Y and dY (copied per panel row-major by k_yd_rows, read one block ahead
+// from Y and dY (copied per panel column by column by k_yd_rows, read one block ahead
 // while the previous block is factorised) and the pending updates of its
 // descendants.  Those live in slots; the second last (ustride - 2) stays zero and is
 // read by the panel entries that receive no update (su_rows gives every entry's
