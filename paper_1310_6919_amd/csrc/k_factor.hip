@@ -376,19 +376,26 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
     __syncthreads();
     double *X = Dinv + bl_dinv[b];
     const int k = threadIdx.x;
-    double xs[64];   // column k of D^{-1}
+    // column k of D^{-1} by forward substitution, in registers (w <= 32: loops of fixed
+    // length, rows beyond w skipped uniformly; the terms j < k add exact zeros)
+    double xs[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) xs[i] = 0.0;
     if (k < w) {
-        // column k of D^{-1} by forward substitution
-        for (int i = 0; i < w; ++i) xs[i] = 0.0;
         const double dk = D[k + w * k];
         if (!(dk != 0.0) || !isfinite(dk)) atomicExch(fail, b + 1);
-        xs[k] = 1.0 / dk;
-        for (int i = k + 1; i < w; ++i) {
-            double acc = 0.0;
-            for (int j = k; j < i; ++j) acc += D[i + w * j] * xs[j];
-            xs[i] = -acc / D[i + w * i];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            if (i < w) {   // uniform
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < i; ++j) acc += D[i + w * j] * xs[j];
+                xs[i] = (i == k) ? 1.0 / dk : ((i > k) ? -acc / D[i + w * i] : 0.0);
+            }
         }
-        for (int i = 0; i < w; ++i) X[i + w * k] = xs[i];
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < w) X[i + w * k] = xs[i];
     }
     if (G && w <= 32 && h <= 64) {
         // G_b = [D^{-1}; P21 D^{-1}] (h x w): D^{-1} (each thread its column), P21 and G
@@ -400,8 +407,11 @@ k_dinv(const int *__restrict__ bl_first, const int64_t *__restrict__ bl_rptr, co
         __syncthreads();
         double *Xs = D, *Ps = D + w * w, *Gs = D + 2048;
         const int hw = h - w;
-        if (k < w)
-            for (int i = 0; i < w; ++i) Xs[i + w * k] = xs[i];
+        if (k < w) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                if (i < w) Xs[i + w * k] = xs[i];
+        }
         for (int i = threadIdx.x; i < hw * w; i += blockDim.x) Ps[i] = P[(w + i % hw) + int64_t(h) * (i / hw)];
         __syncthreads();
         for (int i = threadIdx.x; i < h * w; i += blockDim.x) {
