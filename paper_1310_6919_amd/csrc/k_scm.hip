@@ -197,16 +197,23 @@ k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_p
     }
 }
 
+// out[k] = sum over the parts of part[c n + pos[k]] (pos maps constraint k to its
+// position; null: the identity): 64 outputs per workgroup, each wave a quarter of
+// the parts, the four partial sums added in a fixed order
 __global__ void __launch_bounds__(256)
 k_sum_partials(int n, int nparts, const double *__restrict__ part, const int *__restrict__ pos,
                double *__restrict__ out) {
-    // out[k] = sum over parts of part[., pos[k]] (pos maps constraint k to its position)
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    __shared__ double ps[4][64];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int k = blockIdx.x * 64 + l;
+    double s = 0.0;
+    if (k < n) {
         const int p = pos ? pos[k] : k;
-        double s = 0.0;
-        for (int c = 0; c < nparts; ++c) s += part[int64_t(c) * n + p];
-        out[k] = s;
+        for (int c = wv; c < nparts; c += 4) s += part[int64_t(c) * n + p];
     }
+    ps[wv][l] = s;
+    __syncthreads();
+    if (wv == 0 && k < n) out[k] = (ps[0][l] + ps[1][l]) + (ps[2][l] + ps[3][l]);
 }
 
 // dX on E, block-tiled: for storage block b and a chunk of 256 values of d, partial
@@ -353,7 +360,7 @@ void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *X
     if (d.nzg_mma > 0)
         hipLaunchKernelGGL(k_zm_mma<true>, dim3((d.n + 63) / 64, d.nzg_mma), dim3(256), 0, st, d.n, d.zg_mma,
                            d.zg_ptr, d.zg_rows, d.zg_slot, Mvec, Xh, Yi, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(grid_cap(d.m, 256)), dim3(256), 0, st, d.m, nparts,
+    hipLaunchKernelGGL(k_sum_partials, dim3((d.m + 63) / 64), dim3(256), 0, st, d.m, nparts,
                        (const double *)part, d.had_pos, hcol);
 }
 

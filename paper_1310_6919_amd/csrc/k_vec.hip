@@ -127,11 +127,17 @@ __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const in
     }
 }
 
-__global__ void k_metrics_final(int ng, const double *__restrict__ part, double *__restrict__ scal) {
+// ng <= kMetricsGroups; the partial results are staged in LDS by all lanes (one
+// round of loads), then combined by one thread in group order
+__global__ void __launch_bounds__(64) k_metrics_final(int ng, const double *__restrict__ part,
+                                                      double *__restrict__ scal) {
+    __shared__ double sp[8 * kMetricsGroups];
+    for (int i = threadIdx.x; i < 8 * ng; i += blockDim.x) sp[i] = part[i];
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int g = 0; g < ng; ++g) {
-        const double *pp = part + 8 * g;
+        const double *pp = sp + 8 * g;
         v[0] += pp[0];
         v[1] += pp[1];
         v[2] = fmax(v[2], pp[2]);
