@@ -41,6 +41,8 @@ constexpr int kDualRounds = 2;
 constexpr int kDualTest[kDualRounds] = {511, 384};
 constexpr int kMaxDualRounds = 16;
 constexpr int kCand = 1024;      // the most candidates of a round
+// the phase flags (8 ints), the scalars (16 doubles) and the dual bracket (4 doubles)
+constexpr size_t kReadback = 8 * sizeof(int) + 16 * sizeof(double) + 4 * sizeof(double);
 constexpr int kMaxClique = 64;   // largest clique of the clique kernels (register tiles of 64 x 64)
 constexpr int kMaxPanel = 4096;  // largest storage panel (doubles): 32 KiB of LDS
 constexpr int kMaxM = 65535;     // most constraints
@@ -82,6 +84,11 @@ struct sdpc_handle {
     double *ydw = nullptr, *ydw_dual = nullptr;   // (Y, dY) panel tiles of the Y factor / dual step
     int *flags = nullptr;   // [0..kCand) dual-step candidates, [kCand] dinv, [kCand+1] algorithm 1, [kCand+2]
                             // potrf, [kCand+3] / [kCand+4] algorithm 1 / dinv of the next X, [kCand+5] Y factor
+    // flags, scal and alphas are one device block in that order, so that the phase
+    // flags, the scalars and the dual bracket are contiguous (kReadback bytes from
+    // flags + kCand) and come back in one copy into this pinned host buffer
+    unsigned char *rbh = nullptr;
+    bool flags_zeroed = false;   // the last operation on flags was the clear enqueued after a step's readback
     int64_t ldb = 0;
     double last_alpha[2] = {0, 0};
     double scm_ms[5] = {0, 0, 0, 0, 0};
@@ -220,6 +227,7 @@ void sdpc_destroy(sdpc_handle *h) {
     if (h->ev_dy) (void)hipEventDestroy(h->ev_dy);
     if (h->ev_dual) (void)hipEventDestroy(h->ev_dual);
     if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->rbh) (void)hipHostFree(h->rbh);
     delete h;
 }
 
@@ -844,17 +852,27 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(dalloc(h, &h->pflags_f, size_t(potrf_flow_flag_count(m, m + 1))));
     TRY(dalloc(h, &h->pwork, potrf_work_doubles(m)));
     TRY(dalloc(h, &h->pwork_f, potrf_flow_work_doubles(m)));
-    TRY(dalloc(h, &h->scal, 16));
+    {
+        double *blk = nullptr;   // flags | scal | alphas (kCand + 8 ints is a whole number of doubles)
+        static_assert((kCand + 8) % 2 == 0, "flags must end on a double boundary");
+        TRY(dalloc(h, &blk, size_t(kCand + 8) / 2 + 16 + kCand));
+        h->flags = reinterpret_cast<int *>(blk);
+        h->scal = blk + (kCand + 8) / 2;
+        h->alphas = h->scal + 16;
+        if (hipHostMalloc(reinterpret_cast<void **>(&h->rbh), kReadback, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            h->rbh = nullptr;
+            return fail(h, SDPC_E_OOM, "pinned host allocation of the readback buffer failed");
+        }
+    }
     TRY(dalloc(h, &h->mwork, metrics_work_doubles(m)));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alpha_hi, size_t(S.ncl)));
-    TRY(dalloc(h, &h->alphas, kCand));
     TRY(dalloc(h, &h->cand, ns * kCand));
     TRY(dalloc(h, &h->ubuf, std::max<size_t>(size_t(d.nU), 1) * kCand));
     TRY(dalloc(h, &h->ydw, wave_chol_work_doubles(d)));
     TRY(dalloc(h, &h->ydw_dual, wave_chol_work_doubles(d)));
     TRY(dalloc(h, &h->part, std::max(size_t(2) * dX_chunks(d) * ns, size_t(rhs_had_parts(d)) * n)));
-    TRY(dalloc(h, &h->flags, kCand + 8));
     if (d.cc) TRY(dalloc(h, &h->ccwork, cc_work_doubles(d)));
     HIPCHK(h, hipMemsetAsync(h->Lhat, 0, ns * sizeof(double), h->st));
     HIPCHK(h, hipMemsetAsync(h->N, 0, ns * sizeof(double), h->st));
@@ -966,23 +984,25 @@ int read_flag(sdpc_handle *h, int idx) {
 
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
 // Flags of the phases, checked after the launch sequence has completed.
+// fl_read: the 8 phase flags flags[kCand .. kCand + 8) as already read back, or null
+// to read them here.
 sdpc_status check_flags(sdpc_handle *h, bool potrf, const int *fl_read = nullptr) {
-    int fl[kCand + 8];
+    int fl[8];
     if (fl_read)
         std::memcpy(fl, fl_read, sizeof(fl));
     else
-        HIPCHK(h, hipMemcpy(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost));
-    if (fl[kCand + 5])
-        return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[kCand + 5] - 1) + ")");
-    if (fl[kCand + 1])
-        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[kCand + 1] - 1) + ")");
-    if (fl[kCand + 3])
+        HIPCHK(h, hipMemcpy(fl, h->flags + kCand, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl[5])
+        return fail(h, SDPC_E_NOT_PD, "Y is not positive definite (storage block " + std::to_string(fl[5] - 1) + ")");
+    if (fl[1])
+        return fail(h, SDPC_E_NOT_PD, "clique block of Xbar not positive definite (clique " + std::to_string(fl[1] - 1) + ")");
+    if (fl[3])
         return fail(h, SDPC_E_NOT_PD, "clique block of the updated Xbar not positive definite (clique " +
-                                          std::to_string(fl[kCand + 3] - 1) + ")");
-    if (fl[kCand] || fl[kCand + 4]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
-    if (potrf && fl[kCand + 2] < 0) return fail(h, SDPC_E_HIP, "SCE solve: an internal hand-over wait ran out");
-    if (potrf && fl[kCand + 2])
-        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[kCand + 2] - 1));
+                                          std::to_string(fl[3] - 1) + ")");
+    if (fl[0] || fl[4]) return fail(h, SDPC_E_NOT_PD, "singular diagonal block in a factor");
+    if (potrf && fl[2] < 0) return fail(h, SDPC_E_HIP, "SCE solve: an internal hand-over wait ran out");
+    if (potrf && fl[2])
+        return fail(h, SDPC_E_NOT_PD, "Schur complement matrix not positive definite at pivot " + std::to_string(fl[2] - 1));
     return SDPC_OK;
 }
 
@@ -1023,7 +1043,8 @@ sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, doubl
     DevStruct &d = h->d;
     hipStream_t st = h->st;
     const bool xready = in_step && h->xside_ready;
-    HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
+    if (!(in_step && h->flags_zeroed)) HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
+    h->flags_zeroed = false;
     HIPCHK(h, hipEventRecord(h->evs[0], st));
     if (in_step && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
         HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
@@ -1177,13 +1198,19 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     // the step lengths and the flags: one synchronisation per iteration
     launch_metrics(d, h->Xn, h->Y, h->z, h->G, h->scal, h->mwork, st);
     HIPCHK(h, hipGetLastError());
-    double ap = 0.0, br[4] = {0, 0, 0, -1};
-    int fl[kCand + 8];
-    HIPCHK(h, hipMemcpyAsync(&ap, h->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipMemcpyAsync(br, h->alphas, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipMemcpyAsync(h->msc, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipMemcpyAsync(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    // (one copy into pinned memory; the flags are cleared behind it for the next
+    // iteration, so that its first operation is a kernel)
+    HIPCHK(h, hipMemcpyAsync(h->rbh, h->flags + kCand, kReadback, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
     HIPCHK(h, hipStreamSynchronize(st));
+    h->flags_zeroed = true;
+    int fl[8];
+    double sc[16], br[4];
+    std::memcpy(fl, h->rbh, sizeof(fl));
+    std::memcpy(sc, h->rbh + sizeof(fl), sizeof(sc));
+    std::memcpy(br, h->rbh + sizeof(fl) + sizeof(sc), sizeof(br));
+    std::memcpy(h->msc, sc, sizeof(h->msc));
+    const double ap = sc[8];
     read_scm_timing(h);
     TRY(check_flags(h, true, fl));
     const double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
@@ -1285,6 +1312,7 @@ sdpc_status sdpc_scm(sdpc_handle *h, const double *d_Xbar_E, const double *d_Y_E
 
 sdpc_status sdpc_potrf(sdpc_handle *h, double *d_B, int64_t ldb, int32_t m) {
     if (!h || !d_B || m < 0 || ldb < m || m > h->m) return h ? fail(h, SDPC_E_ARG, "bad sdpc_potrf arguments") : SDPC_E_ARG;
+    h->flags_zeroed = false;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), h->st));
     potrf_rows(h, m, m, d_B, ldb, h->flags + kCand + 2);
     HIPCHK(h, hipGetLastError());
@@ -1392,6 +1420,7 @@ sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
     if (!h) return SDPC_E_ARG;
     DevStruct &d = h->d;
     hipStream_t st = h->st;
+    h->flags_zeroed = false;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand, 0, 8 * sizeof(int), st));
     h->xside_ready = false;
     launch_xside(h, h->X, h->flags + kCand + 1, h->flags + kCand);
@@ -1470,10 +1499,8 @@ sdpc_status sdpc_adjoint(sdpc_handle *h, const double *d_GL_E, const double *d_d
     launch_dX_blocked(d, h->W, h->Yi, h->Xn, 0.0, h->part, d_gC_E, st);
     HIPCHK(h, hipGetLastError());
     h->metrics_ready = false;   // G was used as workspace: the next step recomputes it
-    int fl[kCand + 8];
-    HIPCHK(h, hipMemcpyAsync(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipStreamSynchronize(st));
-    return check_flags(h, true, fl);
+    return check_flags(h, true);
 }
 
 sdpc_status sdpc_get_scm_timing(const sdpc_handle *h, double *ms5) {
