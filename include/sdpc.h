@@ -187,7 +187,10 @@ sdpc_status sdpc_reset(sdpc_handle *h);
 
 /* One iteration (Steps 1-4) from the handle's current iterate.  Returns
  * SDPC_OK after an update; res->status is SDPC_OK when the stopping test
- * already held (no update made). */
+ * already held (no update made).  Unless the gap is already near the stopping
+ * tolerance, the next iteration's Schur complement phase is left enqueued on
+ * the handle's stream when it returns (later calls on the handle are ordered
+ * after it). */
 sdpc_status sdpc_step(sdpc_handle *h, sdpc_result *res);
 
 /* The Schur complement matrix at a given state: Y = N N^T (sparse
@@ -246,16 +249,18 @@ sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double 
  * d_N (Y = N N^T, Section 3.1 type (v)), d_Lhat (X^{-1} = Lhat Lhat^T,
  * Algorithm 1).  After sdpc_scm both belong to the state it was given.
  * Inside sdpc_step / sdpc_solve the next X's Lhat is formed while the dual
- * step runs, so after an iteration d_Lhat already belongs to the new X while
- * d_N still belongs to the Y the iteration started from; call sdpc_scm with
- * the state from sdpc_get_solution for factors of one iterate.  With
+ * step runs, and the next iteration's Schur complement phase is usually
+ * enqueued before the step returns, so after an iteration d_Lhat belongs to
+ * the new X and d_N to the new Y or to the Y the iteration started from; call
+ * sdpc_scm with the state from sdpc_get_solution for factors of one iterate.  With
  * factorization = 1, d_Lhat receives L^{-1} of eq. sparse_fact instead.
  * Either may be NULL.  Synchronises. */
 sdpc_status sdpc_get_factors(const sdpc_handle *h, double *d_N, double *d_Lhat);
 
 /* Dense X^ (max-determinant completion, Section 2.1) and Y^{-1} formed by the
- * last SCM evaluation (sdpc_scm, or the Schur complement phase of the last
- * iteration, i.e. of the iterate that iteration started from), n x n
+ * last SCM evaluation: sdpc_scm, or after sdpc_step / sdpc_solve the Schur
+ * complement phase of the iterate the last iteration started from or, when the
+ * next iteration's phase was enqueued ahead (the usual case), of the new iterate.  n x n
  * column-major in the ELIMINATION order (position i is original index
  * perm[i]).  Either may be NULL.  Synchronises. */
 sdpc_status sdpc_get_dense(const sdpc_handle *h, double *d_Xhat, double *d_Yinv);

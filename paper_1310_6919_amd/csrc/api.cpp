@@ -43,6 +43,9 @@ constexpr int kMaxDualRounds = 16;
 constexpr int kCand = 1024;      // the most candidates of a round
 // the phase flags (8 ints), the scalars (16 doubles) and the dual bracket (4 doubles)
 constexpr size_t kReadback = 8 * sizeof(int) + 16 * sizeof(double) + 4 * sizeof(double);
+// the next iteration's Schur complement phase is enqueued ahead unless the relative
+// gap is already within this factor of the stopping tolerance
+constexpr double kAheadGap = 30.0;
 constexpr int kMaxClique = 64;   // largest clique of the clique kernels (register tiles of 64 x 64)
 constexpr int kMaxPanel = 4096;  // largest storage panel (doubles): 32 KiB of LDS
 constexpr int kMaxM = 65535;     // most constraints
@@ -89,11 +92,16 @@ struct sdpc_handle {
     // flags + kCand) and come back in one copy into this pinned host buffer
     unsigned char *rbh = nullptr;
     bool flags_zeroed = false;   // the last operation on flags was the clear enqueued after a step's readback
+    bool scm_ready = false;      // the Schur complement phase of the current iterate is already enqueued (by
+                                 // the previous step, behind its readback, with N the dual step's twin factor)
     int64_t ldb = 0;
     double last_alpha[2] = {0, 0};
     double scm_ms[5] = {0, 0, 0, 0, 0};
     hipEvent_t ev[8]{};    // phases of an iteration
-    hipEvent_t evs[6]{};   // phases of the SCM evaluation
+    hipEvent_t evs[2][6]{};   // phases of the SCM evaluation, two sets used in turn (the next
+                              // iteration's may be enqueued before this one's are read)
+    int evs_set = 0;          // the set the last SCM evaluation used
+    hipEvent_t ev_rb = nullptr;   // a step's readback has landed in rbh
     hipStream_t side = nullptr;   // second stream (default priority): dual step alongside dX and alpha_p
     hipEvent_t ev_dy = nullptr, ev_dual = nullptr;
     int *pflags_b = nullptr;   // hand-over flags of the SCE backward solve
@@ -222,8 +230,10 @@ void sdpc_destroy(sdpc_handle *h) {
     for (void *p : h->allocs) (void)hipFree(p);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
-    for (auto &e : h->evs)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &set : h->evs)
+        for (auto &e : set)
+            if (e) (void)hipEventDestroy(e);
+    if (h->ev_rb) (void)hipEventDestroy(h->ev_rb);
     if (h->ev_dy) (void)hipEventDestroy(h->ev_dy);
     if (h->ev_dual) (void)hipEventDestroy(h->ev_dual);
     if (h->side) (void)hipStreamDestroy(h->side);
@@ -880,7 +890,9 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     HIPCHK(h, hipMemsetAsync(h->pflags_b, 0, potrf_flag_count(m) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->pflags_f, 0, potrf_flow_flag_count(m, m + 1) * sizeof(int), h->st));
     for (auto &e : h->ev) HIPCHK(h, hipEventCreate(&e));
-    for (auto &e : h->evs) HIPCHK(h, hipEventCreate(&e));
+    for (auto &set : h->evs)
+        for (auto &e : set) HIPCHK(h, hipEventCreate(&e));
+    HIPCHK(h, hipEventCreateWithFlags(&h->ev_rb, hipEventDisableTiming));
     HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     HIPCHK(h, hipEventCreateWithFlags(&h->ev_dy, hipEventDisableTiming));
     HIPCHK(h, hipEventCreateWithFlags(&h->ev_dual, hipEventDisableTiming));
@@ -1006,10 +1018,10 @@ sdpc_status check_flags(sdpc_handle *h, bool potrf, const int *fl_read = nullptr
     return SDPC_OK;
 }
 
-void read_scm_timing(sdpc_handle *h) {
+void read_scm_timing(sdpc_handle *h, int set) {
     for (int i = 0; i < 5; ++i) {
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, h->evs[i], h->evs[i + 1]);
+        (void)hipEventElapsedTime(&ms, h->evs[set][i], h->evs[set][i + 1]);
         h->scm_ms[i] = ms;
     }
 }
@@ -1037,44 +1049,52 @@ void launch_xside(sdpc_handle *h, const double *Xbar, int *fail_clique, int *fai
 // Y = N N^T; Lhat (Algorithm 1); X^ and Y^{-1}; B lower; optional Cholesky of B.
 // Inside an iteration (in_step) the factor of Y may come from the dual step, the
 // X side may already have been formed at the end of the previous iteration, and
-// nothing is synchronised: the caller checks the flags once at its end.
+// nothing is synchronised: the caller checks the flags once at its end.  With
+// twin_on_device the factor of Y is the dual step's twin whose index the dual
+// step left in alphas[3] (the next iteration's phase, enqueued before the host
+// knows the index; if there is none, N is stale and the caller discards the phase).
 sdpc_status scm_phase(sdpc_handle *h, const double *Xbar, const double *Y, double *B, int64_t ldb, bool factor,
-                      bool in_step = false) {
+                      bool in_step = false, bool twin_on_device = false) {
     DevStruct &d = h->d;
     hipStream_t st = h->st;
     const bool xready = in_step && h->xside_ready;
     if (!(in_step && h->flags_zeroed)) HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
     h->flags_zeroed = false;
-    HIPCHK(h, hipEventRecord(h->evs[0], st));
-    if (in_step && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
+    h->scm_ready = false;
+    h->evs_set ^= 1;
+    hipEvent_t *evs = h->evs[h->evs_set];
+    HIPCHK(h, hipEventRecord(evs[0], st));
+    if (twin_on_device)
+        launch_copy_selected(d.nslot, h->cand, h->alphas + 3, kCand, h->N, st);
+    else if (in_step && h->next_cand >= 0)   // N = the dual step's twin factor of this Y
         HIPCHK(h, hipMemcpyAsync(h->N, h->cand + size_t(h->next_cand) * size_t(d.nslot),
                                  size_t(d.nslot) * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
         launch_sn_chol(d, Y, h->N, h->ubuf, h->ydw, h->flags + kCand + 5, st);
     h->next_cand = -1;
     launch_dinv(d, h->N, h->DinvN, h->flags + kCand, st, h->GN);
-    HIPCHK(h, hipEventRecord(h->evs[1], st));
+    HIPCHK(h, hipEventRecord(evs[1], st));
     if (!xready) launch_xside(h, Xbar, h->flags + kCand + 1, h->flags + kCand);
-    HIPCHK(h, hipEventRecord(h->evs[2], st));
+    HIPCHK(h, hipEventRecord(evs[2], st));
     // Y^{-1} and X^ in one launch: the two walks are latency-bound and fill each
     // other's idle compute units
     launch_inverse_by_solves(d, h->N, h->DinvN, h->Yi, h->Lhat, h->DinvL, h->Xh, st, nullptr, h->Dblk, h->GN,
                              h->GL);
     h->xside_ready = false;
-    HIPCHK(h, hipEventRecord(h->evs[3], st));
+    HIPCHK(h, hipEventRecord(evs[3], st));
     if (d.hadamard)
         launch_scm_hadamard(d, h->Xh, h->Yi, B, ldb, st);
     else if (d.cc)
         launch_scm_cc(d, h->Xh, h->Yi, h->W, h->ccwork, B, ldb, st);
     else
         launch_scm_general(d, h->kq_ptr_h.data(), h->Xh, h->Yi, h->W, h->T, B, ldb, st);
-    HIPCHK(h, hipEventRecord(h->evs[4], st));
+    HIPCHK(h, hipEventRecord(evs[4], st));
     if (factor) potrf_rows(h, d.m, d.m, B, ldb, h->flags + kCand + 2);
-    HIPCHK(h, hipEventRecord(h->evs[5], st));
+    HIPCHK(h, hipEventRecord(evs[5], st));
     HIPCHK(h, hipGetLastError());
     if (in_step) return SDPC_OK;
     HIPCHK(h, hipStreamSynchronize(st));
-    read_scm_timing(h);
+    read_scm_timing(h, h->evs_set);
     return check_flags(h, factor);
 }
 
@@ -1155,7 +1175,9 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
         return SDPC_OK;
     }
     const double bm = (mu_target > 0.0) ? mu_target : it.beta * it.mu;
-    TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false, true));
+    if (!h->scm_ready) TRY(scm_phase(h, h->X, h->Y, h->B, h->ldb, false, true));
+    h->scm_ready = false;
+    const int evs_set = h->evs_set;
     hipEvent_t *ev = h->ev;
     HIPCHK(h, hipEventRecord(ev[0], st));
     // right-hand side: g = b - beta mu A(Y^{-1}) + A(X^ G Y^{-1})
@@ -1202,8 +1224,20 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     // iteration, so that its first operation is a kernel)
     HIPCHK(h, hipMemcpyAsync(h->rbh, h->flags + kCand, kReadback, hipMemcpyDeviceToHost, st));
     HIPCHK(h, hipMemsetAsync(h->flags, 0, (kCand + 8) * sizeof(int), st));
-    HIPCHK(h, hipStreamSynchronize(st));
+    HIPCHK(h, hipEventRecord(h->ev_rb, st));
     h->flags_zeroed = true;
+    // Behind the readback, the next iteration's Schur complement phase, on the
+    // assumption that this iteration succeeds and the dual step leaves the factor
+    // of the new Y (the X side of the new X is already formed): the device goes
+    // on while the host reads the step back.  It writes only N, the inverses and
+    // B, which the next iteration recomputes if the assumption fails.  Skipped
+    // near the stopping test, where the next iteration is likely not to run.
+    const bool ahead = (mu_target > 0.0) || !(it.relgap <= kAheadGap * h->prm.gap_tol);
+    if (ahead) {
+        h->xside_ready = true;   // Lhat of Xn is enqueued above
+        TRY(scm_phase(h, h->Xn, h->Y, h->B, h->ldb, false, true, true));
+    }
+    HIPCHK(h, hipEventSynchronize(h->ev_rb));
     int fl[8];
     double sc[16], br[4];
     std::memcpy(fl, h->rbh, sizeof(fl));
@@ -1211,7 +1245,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     std::memcpy(br, h->rbh + sizeof(fl) + sizeof(sc), sizeof(br));
     std::memcpy(h->msc, sc, sizeof(h->msc));
     const double ap = sc[8];
-    read_scm_timing(h);
+    read_scm_timing(h, evs_set);
     TRY(check_flags(h, true, fl));
     const double t_scm = h->scm_ms[0] + h->scm_ms[1] + h->scm_ms[2] + h->scm_ms[3];
     float ms_rhs = 0, ms_chol = 0, ms_pm = 0, ms_potrf = 0;
@@ -1230,6 +1264,10 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     h->metrics_ready = true;
     h->xside_ready = true;
     h->next_cand = (br[3] >= 0.0) ? int(br[3]) : -1;
+    if (ahead && h->next_cand >= 0) {   // the phase enqueued ahead belongs to the new iterate
+        h->scm_ready = true;
+        h->next_cand = -1;
+    }
     h->iters++;
     if (res) {
         res->t_scm_ms += t_scm + ms_rhs;
@@ -1260,6 +1298,7 @@ sdpc_status sdpc_reset(sdpc_handle *h) {
     h->next_cand = -1;
     h->xside_ready = false;
     h->metrics_ready = false;
+    h->scm_ready = false;
     return SDPC_OK;
 }
 
@@ -1378,6 +1417,7 @@ sdpc_status sdpc_set_state(sdpc_handle *h, const double *d_Xbar_E, const double 
     h->next_cand = -1;
     h->xside_ready = false;
     h->metrics_ready = false;
+    h->scm_ready = false;
     return SDPC_OK;
 }
 
@@ -1421,6 +1461,7 @@ sdpc_status sdpc_complete_dense(sdpc_handle *h, double *d_Xhat) {
     DevStruct &d = h->d;
     hipStream_t st = h->st;
     h->flags_zeroed = false;
+    h->scm_ready = false;
     HIPCHK(h, hipMemsetAsync(h->flags + kCand, 0, 8 * sizeof(int), st));
     h->xside_ready = false;
     launch_xside(h, h->X, h->flags + kCand + 1, h->flags + kCand);

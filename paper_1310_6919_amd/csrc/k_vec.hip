@@ -168,6 +168,19 @@ __global__ void k_axpy_checked(int64_t len, const double *x, const double *__res
     }
 }
 
+// out = candidate sel[0] of a pool of ncand vectors of length len, where the
+// index was left on the device as a double by an earlier kernel; a negative or
+// out-of-range index leaves out as it is.
+__global__ void k_copy_selected(int64_t len, const double *__restrict__ pool, const double *__restrict__ sel,
+                                int ncand, double *__restrict__ out) {
+    const double c = sel[0];
+    if (!(c >= 0.0) || !(c < double(ncand))) return;
+    const double *__restrict__ src = pool + int64_t(c) * len;
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < len;
+         s += int64_t(gridDim.x) * blockDim.x)
+        out[s] = src[s];
+}
+
 // out(i, j) = in(pos[i], pos[j]): a dense n x n column-major matrix from the
 // elimination order back to the original indices
 __global__ void __launch_bounds__(256) k_unpermute(int n, const int *__restrict__ pos, const double *__restrict__ in,
@@ -231,6 +244,12 @@ void launch_axpy_checked(int64_t len, const double *x, const double *dx, const d
                          double scale, const int *flags, int nflag, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy_checked, dim3(grid_for(len)), dim3(kThreads), 0, st, len, x, dx, alpha, alpha2, scale,
                        flags, nflag, out);
+}
+
+void launch_copy_selected(int64_t len, const double *pool, const double *sel, int ncand, double *out,
+                          hipStream_t st) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_copy_selected, dim3(grid_for(len)), dim3(kThreads), 0, st, len, pool, sel, ncand, out);
 }
 
 void launch_add(int64_t len, const double *a, const double *b, double *out, hipStream_t st) {

@@ -159,6 +159,10 @@ void launch_metrics(const DevStruct &d, const double *X, const double *Y, const 
 // alpha2[0] when given) are positive, else out = x; out may be x
 void launch_axpy_checked(int64_t len, const double *x, const double *dx, const double *alpha, const double *alpha2,
                          double scale, const int *flags, int nflag, double *out, hipStream_t st);
+// out = pool + sel[0] * len (ncand vectors of length len; sel[0] a device double,
+// the index; negative or >= ncand: out untouched)
+void launch_copy_selected(int64_t len, const double *pool, const double *sel, int ncand, double *out,
+                          hipStream_t st);
 // out = a + b elementwise (b == nullptr: out = a)
 void launch_add(int64_t len, const double *a, const double *b, double *out, hipStream_t st);
 // out(i, j) = in(pos[i], pos[j]) for dense n x n column-major matrices
