@@ -10,7 +10,9 @@
   * sdpc_complete_dense (the max-determinant completion of the current
     iterate, Section 2.1) against the oracle's completion;
   * a failed iteration leaves the iterate untouched;
-  * two identical solves are bit for bit identical.
+  * two identical solves are bit for bit identical;
+  * the Schur complement phase a step enqueues ahead is dropped when the state
+    changes, and calls between steps leave the iterates as they would be.
 
 Tolerances as in test_gpu_parity (1e-10 relative to max |B| for states with
 cond <= ~50).
@@ -233,6 +235,67 @@ def test_solves_are_bitwise_reproducible(name):
         assert o[0] == out[0][0] and o[1] == out[0][1] and o[2] == out[0][2]
         for a, b in zip(o[3:], out[0][3:]):
             assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------- the phase enqueued ahead
+@pytest.mark.parametrize("name", ["band_ragged", "normmin", "random_sdp"])
+def test_state_set_between_steps_discards_phase_enqueued_ahead(name):
+    """A step leaves the next iteration's Schur complement phase enqueued (for the
+    iterate it produced); a new state set before the next step must not use it:
+    that step's direction is the oracle's at the new state."""
+    prob = CASES[name]()
+    h = _create(prob)
+    h.sdpc_reset()
+    h.sdpc_step()
+    h.sdpc_step()
+    rng = np.random.default_rng(23)
+    Xfull, Y = _state(prob, rng)
+    z = rng.standard_normal(prob.m) * 0.1
+    h.sdpc_set_state(dev(to_E(h, Xfull)), dev(to_E(h, Y)), dev(z))
+    h.sdpc_step()
+    dz, dX, dY, (ap, ad) = h.sdpc_get_direction()
+    rows, cols = aggregate_pattern(prob)
+    ch = chordal_structure(prob.n, rows, cols)
+    A = oracle.pdipm.permuted_mats(prob, ch)
+    ref = oracle.mc_direction(ch, A, prob.b, np.where(ch.E_mask(), Xfull, 0.0), Y, z)
+    assert rel_err(host(dz), ref["dz"]) <= 1e-9
+    assert rel_err(from_E(h, host(dY)), ref["dY"]) <= 1e-9
+    assert rel_err(from_E(h, host(dX)), ref["dX"]) <= 1e-9
+    assert abs(ap - ref["alpha_p"]) <= 1e-9 * max(1.0, ref["alpha_p"])
+    assert ref["alpha_d"] * (1 - 1e-4) <= ad <= ref["alpha_d"] * (1 + 1e-12)
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["band_ragged", "normmin"])
+def test_calls_between_steps_leave_the_iterates(name):
+    """sdpc_complete_dense, sdpc_scm, sdpc_get_factors and sdpc_get_dense between
+    steps overwrite the buffers of the phase a step enqueued ahead; the following
+    steps recompute it and the iterates stay those of uninterrupted steps (up to
+    the rounding of the Y factor, formed afresh instead of taken from the dual
+    step's twin)."""
+    prob = CASES[name]()
+    ref = _create(prob)
+    ref.sdpc_reset()
+    for _ in range(5):
+        ref.sdpc_step()
+    want = _snapshot(ref)
+    ref.close()
+    h = _create(prob)
+    h.sdpc_reset()
+    h.sdpc_step()
+    h.sdpc_complete_dense()
+    h.sdpc_step()
+    X_E, Y_E, _ = h.sdpc_get_solution()
+    B = h.sdpc_scm(X_E, Y_E)
+    assert np.isfinite(host(B)).all()
+    h.sdpc_step()
+    h.sdpc_get_factors()
+    h.sdpc_get_dense()
+    h.sdpc_step()
+    h.sdpc_step()
+    for a, b in zip(_snapshot(h), want):
+        assert rel_err(a, b) <= 1e-10
+    h.close()
 
 
 # ----------------------------------------------------------------- storage blocks
