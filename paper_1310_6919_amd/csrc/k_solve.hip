@@ -21,7 +21,8 @@
 // most 32 wide and 64 high).  The next block's operands are loaded while the
 // current block is processed, so a walk pays one memory latency at its start
 // instead of one per block.  Finally the lower triangle is mirrored to make the
-// output symmetric.
+// output symmetric: by a separate pass after k_inv_solve_mma and k_inv_solve, while
+// k_walk_g stores each entry below the diagonal at both places as it is found.
 //
 // The earlier factorisation X^ = L^T D L (Section 2.1, eq. sparse_fact) runs
 // through the same walks with the sparse unit-lower L^{-1} as the factor: the
@@ -707,6 +708,9 @@ k_inv_solve_mma(int n, int nb, int maxw, int maxh, int pcap, const int *__restri
 // than the first block that updates the slot's current row (blocks a tile skips
 // write nothing).  The host frees a slot one block after its last use (SolveSlots),
 // so no step reads a slot as one of its own rows while writing it as a row below.
+// The output is stored symmetric: an entry (i, j) below the diagonal at (i, j) and
+// (j, i), entries above it not at all (the forward results z, parked in `out` for
+// the backward walk, vanish there and are taken as zeros).
 // Limits: every block at most 32 columns wide and 64 rows high.
 struct WalkDesc {
     int F, w, h, sub;
@@ -828,8 +832,8 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
                 os[r] = (orow >= w) ? cur.os[r] : -1;   // -1 beyond the block already
                 const int sc = max(os[r], 0);
                 const double old = (os[r] >= 0 && lwb[sc] >= cur.ob[r]) ? accf[sc * T + li] : 0.0;
-                if (orow < w) {
-                    if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
+                if (orow < w) {   // z, lower triangle only (z vanishes above the diagonal)
+                    if (k0 + li < n && F + orow >= k0 + li) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
                 } else if (os[r] >= 0) {
                     accf[sc * T + li] = old - acc[r];
                 }
@@ -903,7 +907,7 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int ent = lt + 128 * j, k = ent & 31, c = ent >> 5;
-            zslot[c * ZLD + k] = (on && k < e.w && k0 + c < n) ? zs[j] : 0.0;
+            zslot[c * ZLD + k] = (on && k < e.w && k0 + c < n && e.F + k >= k0 + c) ? zs[j] : 0.0;
         }
     };
     double zs0[4], zs1[4];   // loader register sets: block q in set q & 1
@@ -950,7 +954,12 @@ k_walk_g(int n, int nb, const int *__restrict__ bl_first, const int64_t *__restr
                 for (int r = 0; r < 4; ++r) {
                     const int orow = 16 * wv + 4 * r + lq;
                     if (orow < w) {
-                        if (k0 + li < n) out[int64_t(n) * (k0 + li) + F + orow] = acc[r];
+                        // (i, j) below the diagonal is stored twice, at (i, j) and (j, i)
+                        // (rows of the output: 16 consecutive columns per lane group);
+                        // above it nothing: the column of i stores it
+                        const int i = F + orow, j = k0 + li;
+                        if (j < n && i >= j) out[int64_t(n) * j + i] = acc[r];
+                        if (j < n && i > j) out[j + int64_t(n) * i] = acc[r];
                         if (bc.os[r] >= 0) accb[bc.os[r] * T + li] = acc[r];
                     }
                 }
@@ -1040,8 +1049,7 @@ void launch_inverse_by_solves(const DevStruct &d, const double *L0, const double
     if (!d.solve_generic && G0 && (nf == 1 || G1) && walk_g_ok(d)) {   // any Dm is inside G
         hipLaunchKernelGGL(k_walk_g, dim3((d.n + kRhs - 1) / kRhs, nf), dim3(kThreads), walk_g_lds(d), st, d.n, d.nb,
                            d.bl_first, d.bl_rptr, d.bl_subfirst, d.wk_fs, d.wk_fb, d.wk_bs, d.col_block,
-                           d.wk_nfwd, d.wk_nbwd, G0, out0, G1, out1);
-        hipLaunchKernelGGL(k_mirror, dim3(nt, nt, nf), dim3(256), 0, st, d.n, out0, out1);
+                           d.wk_nfwd, d.wk_nbwd, G0, out0, G1, out1);   // both triangles
         return;
     }
     if (!d.solve_generic && solve_mma_ok(d)) {
