@@ -1229,9 +1229,10 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
     // Behind the readback, the next iteration's Schur complement phase, on the
     // assumption that this iteration succeeds and the dual step leaves the factor
     // of the new Y (the X side of the new X is already formed): the device goes
-    // on while the host reads the step back.  It writes only N, the inverses and
-    // B, which the next iteration recomputes if the assumption fails.  Skipped
-    // near the stopping test, where the next iteration is likely not to run.
+    // on while the host reads the step back.  It writes only the factor of Y and
+    // its diagonal inverses, X^, Y^{-1}, B and the assembly's work space, which
+    // the next iteration recomputes if the assumption fails.  Skipped near the
+    // stopping test, where the next iteration is likely not to run.
     const bool ahead = (mu_target > 0.0) || !(it.relgap <= kAheadGap * h->prm.gap_tol);
     if (ahead) {
         h->xside_ready = true;   // Lhat of Xn is enqueued above
