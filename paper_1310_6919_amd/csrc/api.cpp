@@ -794,6 +794,27 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.con_pj, con_pj));
     TRY(upload(h, &d.con_slot, con_slot));
     TRY(upload(h, &d.con_val, con_val));
+    {   // chunks of the long constraints (see kConLong)
+        int64_t longest = 0;
+        for (int k = 0; k < m; ++k) longest = std::max(longest, con_ptr[k + 2] - con_ptr[k + 1]);
+        if (longest > kConLong) {
+            std::vector<int> ch_con, ch_ptr(size_t(m) + 1, 0);
+            std::vector<int64_t> ch_beg;
+            for (int k = 0; k < m; ++k) {
+                const int64_t len = con_ptr[k + 2] - con_ptr[k + 1];
+                const int64_t nch = std::max<int64_t>(1, (len + kConChunk - 1) / kConChunk);
+                for (int64_t c = 0; c < nch; ++c) {
+                    ch_con.push_back(k);
+                    ch_beg.push_back(con_ptr[k + 1] + c * kConChunk);
+                }
+                ch_ptr[k + 1] = int(ch_con.size());
+            }
+            d.con_chunks = int(ch_con.size());
+            TRY(upload(h, &d.ch_con, ch_con));
+            TRY(upload(h, &d.ch_beg, ch_beg));
+            TRY(upload(h, &d.ch_ptr, ch_ptr));
+        }
+    }
     std::vector<double> bvec(prob->b, prob->b + m);
     TRY(upload(h, &d.b, bvec));
     TRY(upload(h, &d.had_pos, had_pos));
@@ -875,7 +896,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             return fail(h, SDPC_E_OOM, "pinned host allocation of the readback buffer failed");
         }
     }
-    TRY(dalloc(h, &h->mwork, metrics_work_doubles(m)));
+    TRY(dalloc(h, &h->mwork, metrics_work_doubles(d)));
     TRY(dalloc(h, &h->alpha_cl, size_t(S.ncl)));
     TRY(dalloc(h, &h->alpha_hi, size_t(S.ncl)));
     TRY(dalloc(h, &h->cand, ns * kCand));
@@ -1187,7 +1208,7 @@ sdpc_status step_impl(sdpc_handle *h, sdpc_result *res, bool *done, double mu_ta
         launch_scm_cc_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->ccwork, h->hcol, st);
     else
         launch_scm_extra_column(d, h->G, h->Xh, h->Yi, h->W, h->T, h->hcol, st);
-    launch_rhs(d, h->Yi, h->hcol, bm, h->g, st);
+    launch_rhs(d, h->Yi, h->hcol, bm, h->g, h->mwork, st);
     HIPCHK(h, hipEventRecord(ev[1], st));
     HIPCHK(h, hipMemsetAsync(h->flags + kCand + 2, 0, sizeof(int), st));
     launch_set_row(d.m, h->g, h->B + d.m, h->ldb, st);

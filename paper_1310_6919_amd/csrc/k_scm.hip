@@ -375,7 +375,9 @@ void launch_dX_blocked(const DevStruct &d, const double *Z, const double *Yi, co
                        d.slot_col, (const double *)part, Yi, Xbar, beta_mu, dX);
 }
 
-void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g, hipStream_t st) {
+void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g, double *work,
+                hipStream_t st) {
+    if (launch_con_chunks(d, true, Yi, beta_mu, h, g, work, st)) return;
     hipLaunchKernelGGL(k_rhs, dim3(grid_cap(d.m, 4)), dim3(256), 0, st, d.m, d.n, d.con_ptr, d.con_pi, d.con_pj,
                        d.con_val, d.b, Yi, h, beta_mu, g);
 }

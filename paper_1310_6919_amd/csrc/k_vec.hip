@@ -85,6 +85,42 @@ __global__ void __launch_bounds__(256) k_con_resid(int m, const int64_t *__restr
     }
 }
 
+// Long constraints, chunk by chunk: workgroup c sums con_val[e] v(e) over the entries
+// of chunk c, each thread over its entries in order, the threads combined in a fixed
+// order (v(e) = v[con_slot[e]], or v(pi, pj) of a dense n x n matrix with DENSE)
+template <bool DENSE>
+__global__ void __launch_bounds__(256) k_con_chunk(const int *__restrict__ ch_con, const int64_t *__restrict__ ch_beg,
+                                                 const int64_t *__restrict__ con_ptr, const int *__restrict__ con_slot,
+                                                 const int *__restrict__ con_pi, const int *__restrict__ con_pj,
+                                                 const double *__restrict__ con_val, const double *__restrict__ v,
+                                                 int n, double *__restrict__ part) {
+    __shared__ double ws[4];
+    const int c = blockIdx.x, k = ch_con[c];
+    const int64_t beg = ch_beg[c];
+    const int64_t lim = beg + int64_t(kConChunk), end = (con_ptr[k + 2] < lim) ? con_ptr[k + 2] : lim;
+    double a = 0.0;
+    for (int64_t e = beg + threadIdx.x; e < end; e += 256) {
+        const double x = DENSE ? v[con_pi[e] + int64_t(n) * con_pj[e]] : v[con_slot[e]];
+        a = fma(con_val[e], x, a);
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[c] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// out[k] = b_k - coef (the chunk sums of constraint k, in order) + add[k]
+__global__ void __launch_bounds__(256) k_con_finish(int m, const int *__restrict__ ch_ptr,
+                                                  const double *__restrict__ part, const double *__restrict__ b,
+                                                  double coef, const double *__restrict__ add,
+                                                  double *__restrict__ out) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = ch_ptr[k]; c < ch_ptr[k + 1]; ++c) s += part[c];
+        out[k] = b[k] - coef * s + (add ? add[k] : 0.0);
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_metrics(int m, int64_t nslot, const int64_t *__restrict__ con_ptr,
                                                   const int *__restrict__ con_slot,
                                                   const double *__restrict__ con_val,
@@ -225,14 +261,31 @@ void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, 
                        d.asm_k, d.asm_val, y, a0, c1, in1, out);
 }
 
-size_t metrics_work_doubles(int m) { return size_t(8) * kMetricsGroups + size_t(m > 0 ? m : 1); }
+size_t metrics_work_doubles(const DevStruct &d) {
+    return size_t(8) * kMetricsGroups + size_t(d.m > 0 ? d.m : 1) + size_t(d.con_chunks);
+}
+
+bool launch_con_chunks(const DevStruct &d, bool dense, const double *v, double coef, const double *add,
+                       double *out, double *work, hipStream_t st) {
+    if (d.con_chunks <= 0 || d.m <= 0) return false;
+    double *part = work + 8 * kMetricsGroups + d.m;
+    if (dense)
+        hipLaunchKernelGGL(k_con_chunk<true>, dim3(d.con_chunks), dim3(256), 0, st, d.ch_con, d.ch_beg, d.con_ptr,
+                           d.con_slot, d.con_pi, d.con_pj, d.con_val, v, d.n, part);
+    else
+        hipLaunchKernelGGL(k_con_chunk<false>, dim3(d.con_chunks), dim3(256), 0, st, d.ch_con, d.ch_beg, d.con_ptr,
+                           d.con_slot, d.con_pi, d.con_pj, d.con_val, v, d.n, part);
+    hipLaunchKernelGGL(k_con_finish, dim3((d.m + 255) / 256), dim3(256), 0, st, d.m, d.ch_ptr, (const double *)part,
+                       d.b, coef, add, out);
+    return true;
+}
 
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z, double *G,
                     double *scal, double *work, hipStream_t st) {
     // G = A_0 - sum z_k A_k - Y
     launch_assemble(d, z, 1.0, -1.0, Y, G, st);
     double *resid = work + 8 * kMetricsGroups;
-    if (d.m > 0)
+    if (d.m > 0 && !launch_con_chunks(d, false, X, 1.0, nullptr, resid, work, st))
         hipLaunchKernelGGL(k_con_resid, dim3((d.m + 3) / 4 < 4096 ? (d.m + 3) / 4 : 4096), dim3(256), 0, st, d.m,
                            d.con_ptr, d.con_slot, d.con_val, d.b, X, resid);
     hipLaunchKernelGGL(k_metrics, dim3(kMetricsGroups), dim3(1024), 0, st, d.m, d.nslot, d.con_ptr, d.con_slot,

@@ -94,6 +94,12 @@ struct DevStruct {
     const int64_t *con_ptr = nullptr;   // m + 2
     const int *con_pi = nullptr, *con_pj = nullptr, *con_slot = nullptr;
     const double *con_val = nullptr;
+    // constraints longer than kConLong entries (when any is): the entries of each
+    // constraint cut into chunks of kConChunk, chunk c belonging to ch_con[c] and
+    // starting at entry ch_beg[c]; constraint k's chunks are ch_ptr[k] .. ch_ptr[k+1]-1
+    int con_chunks = 0;                 // 0: one wave per constraint instead
+    const int *ch_con = nullptr, *ch_ptr = nullptr;
+    const int64_t *ch_beg = nullptr;
     const double *b = nullptr;          // m
     // Schur complement: single diagonal entry per A_k (max-cut form)
     int hadamard = 0;
@@ -151,7 +157,14 @@ constexpr int kZmRows = 128;
 // out[s] = sum_t asm_val[t] * coef_k  + c1 * in1[s]; coef_0 = a0, coef_k = -y[k-1]
 void launch_assemble(const DevStruct &d, const double *y, double a0, double c1, const double *in1,
                      double *out, hipStream_t st);
-size_t metrics_work_doubles(int m);   // work of launch_metrics
+size_t metrics_work_doubles(const DevStruct &d);   // work of launch_metrics and launch_rhs
+constexpr int kConLong = 256, kConChunk = 1024;
+// With chunks (d.con_chunks > 0): out[k] = b_k - coef sum_e con_val[e] v(e) + (add ? add[k] : 0)
+// over the entries of constraint k, v(e) = v[con_slot[e]] (an E-vector) or, dense,
+// v(pi, pj) of an n x n matrix; the chunk sums in work + 8 kMetricsGroups + m.
+// Returns false (nothing launched) without chunks.
+bool launch_con_chunks(const DevStruct &d, bool dense, const double *v, double coef, const double *add,
+                       double *out, double *work, hipStream_t st);
 // scal[...] <- pobj, dobj, max|r|, max|G|, X.Y, also G_E (see k_vec.hip)
 void launch_metrics(const DevStruct &d, const double *X, const double *Y, const double *z,
                     double *G, double *scal, double *work, hipStream_t st);
@@ -243,7 +256,7 @@ void launch_scm_extra_column(const DevStruct &d, const double *Mvec, const doubl
                              const double *Yi, double *W, double *T, double *col, hipStream_t st);
 // g_p = b_p - beta mu A_p . Y^{-1} + h_p
 void launch_rhs(const DevStruct &d, const double *Yi, const double *h, double beta_mu, double *g,
-                hipStream_t st);
+                double *work, hipStream_t st);
 // dX on E:  beta mu Y^{-1} - Xbar - sym(X^ dY Y^{-1}) with W = X^ dY (row-major)
 void launch_dX(const DevStruct &d, const double *W, const double *Yi, const double *Xbar,
                double beta_mu, double *dX, hipStream_t st);
