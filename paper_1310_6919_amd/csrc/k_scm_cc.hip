@@ -150,6 +150,45 @@ k_cc_q(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *__
 // The same for |C| <= 16 with the lanes over the entries of the segment (long rows
 // are not one serial chain): every lane keeps |C| partial sums of each product,
 // reduced over the wave in a fixed order.
+// Segments of at most kShortSeg entries go to k_cc_q16_short, one lane per segment
+// over its entries in order (a wave per segment would idle most of its lanes and
+// spend its time on the reductions); k_cc_q16 takes the longer ones.
+constexpr int kShortSeg = 64;
+
+__global__ void __launch_bounds__(256)
+k_cc_q16_short(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *__restrict__ seg_row,
+               const int64_t *__restrict__ seg_ptr, const int *__restrict__ seg_col,
+               const double *__restrict__ seg_val, const int *__restrict__ seg_slot, const double *__restrict__ Mvec,
+               int qfix, const double *__restrict__ YC, const double *__restrict__ XC, double *__restrict__ Q,
+               double *__restrict__ Qp) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < nseg; s += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t t0 = seg_ptr[s], t1 = seg_ptr[s + 1];
+        if (t1 - t0 > kShortSeg) continue;   // k_cc_q16's
+        const int q = seg_q ? seg_q[s] : qfix;
+        const int i = seg_row ? seg_row[s] : int(s);
+        double ay[16], ax[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) ay[c] = ax[c] = 0.0;
+        for (int64_t t = t0; t < t1; ++t) {
+            const int j = seg_col[t];
+            const double v = seg_slot ? Mvec[seg_slot[t]] : seg_val[t];
+            const double *yc = YC + int64_t(nc) * j, *xc = XC + int64_t(nc) * j;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < nc) {
+                    ay[c] = fma(v, yc[c], ay[c]);
+                    ax[c] = fma(v, xc[c], ax[c]);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < nc) {
+                Q[int64_t(q) * n * nc + i + int64_t(n) * c] = ay[c];
+                Qp[int64_t(q) * n * nc + i + int64_t(n) * c] = ax[c];
+            }
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_cc_q16(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *__restrict__ seg_row,
          const int64_t *__restrict__ seg_ptr, const int *__restrict__ seg_col, const double *__restrict__ seg_val,
@@ -158,9 +197,10 @@ k_cc_q16(int64_t nseg, int n, int nc, const int *__restrict__ seg_q, const int *
     const int lane = threadIdx.x & 63;
     const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
     for (int64_t s = blockIdx.x * int64_t(blockDim.x >> 6) + (threadIdx.x >> 6); s < nseg; s += waves) {
+        const int64_t t0 = seg_ptr[s], t1 = seg_ptr[s + 1];
+        if (t1 - t0 <= kShortSeg) continue;   // k_cc_q16_short's
         const int q = seg_q ? seg_q[s] : qfix;
         const int i = seg_row ? seg_row[s] : int(s);
-        const int64_t t0 = seg_ptr[s], t1 = seg_ptr[s + 1];
         double ay[16], ax[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) ay[c] = ax[c] = 0.0;
@@ -323,6 +363,10 @@ void launch_scm_cc(const DevStruct &d, const double *Xh, const double *Yi, doubl
         hipLaunchKernelGGL(k_gemm_nn, dim3((n + 63) / 64, (m * nc + 63) / 64, 2), dim3(256), 0, st, n, m * nc, n, Xh,
                            Yi, int64_t(n), d.ucat, int64_t(n), w.P, w.Pp, int64_t(n));
         hipLaunchKernelGGL(k_zero, dim3(grid_for(2 * blk * (m + 1), 256)), dim3(256), 0, st, 2 * blk * (m + 1), w.Q);
+        if (nc <= 16)
+            hipLaunchKernelGGL(k_cc_q16_short, dim3(grid_for(d.nseg, 256)), dim3(256), 0, st, d.nseg, n, nc, d.seg_q,
+                               d.seg_row, d.seg_ptr, d.seg_col, d.seg_val, (const int *)nullptr,
+                               (const double *)nullptr, 0, w.YC, w.XC, w.Q, w.Qp);
         hipLaunchKernelGGL(nc <= 16 ? k_cc_q16 : k_cc_q, dim3(grid_for(d.nseg, 4)), dim3(256), 0, st, d.nseg, n, nc,
                            d.seg_q, d.seg_row, d.seg_ptr, d.seg_col, d.seg_val, (const int *)nullptr,
                            (const double *)nullptr, 0, w.YC, w.XC, w.Q, w.Qp);
@@ -352,6 +396,10 @@ void launch_scm_cc_extra_column(const DevStruct &d, const double *Mvec, const do
         hipLaunchKernelGGL(k_zero, dim3(grid_for(blk, 256)), dim3(256), 0, st, blk, w.Q + blk * m);
         hipLaunchKernelGGL(k_zero, dim3(grid_for(blk, 256)), dim3(256), 0, st, blk, w.Qp + blk * m);
         // rows of G: by symmetry, column j of the aggregate pattern lists the entries of row j
+        if (nc <= 16)
+            hipLaunchKernelGGL(k_cc_q16_short, dim3(grid_for(n, 256)), dim3(256), 0, st, int64_t(n), n, nc,
+                               (const int *)nullptr, (const int *)nullptr, d.ag_cptr, d.ag_row,
+                               (const double *)nullptr, d.ag_slot, Mvec, m, w.YC, w.XC, w.Q, w.Qp);
         hipLaunchKernelGGL(nc <= 16 ? k_cc_q16 : k_cc_q, dim3(grid_for(n, 4)), dim3(256), 0, st, int64_t(n), n, nc,
                            (const int *)nullptr, (const int *)nullptr, d.ag_cptr, d.ag_row, (const double *)nullptr,
                            d.ag_slot, Mvec, m, w.YC, w.XC, w.Q, w.Qp);
