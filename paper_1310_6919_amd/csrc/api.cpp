@@ -745,8 +745,33 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
             }
         zg_ptr[g + 1] = zg_ptr[g] + K;
     }
-    d.nzg = nzg;
+    // groups with a long union cut into pieces (split K; see kZmSplit)
+    std::vector<int64_t> vg_ptr(1, 0);
+    std::vector<int> vg_col, vg_piece, zs_g, zs_ptr(1, 0);
+    int npiece = 0;
+    for (int g = 0; g < nzg; ++g) {
+        const int64_t a = zg_ptr[g], b = zg_ptr[g + 1];
+        if (b - a > kZmSplit) {
+            for (int64_t s = a; s < b; s += kZmPiece) {
+                vg_ptr.push_back(std::min(b, s + kZmPiece));
+                vg_col.push_back(g);
+                vg_piece.push_back(npiece++);
+            }
+            zs_g.push_back(g);
+            zs_ptr.push_back(npiece);
+        } else {
+            vg_ptr.push_back(b);
+            vg_col.push_back(g);
+            vg_piece.push_back(-1);
+        }
+    }
+    zg_ptr.swap(vg_ptr);
+    zg_mma.resize(vg_col.size());
+    for (size_t v = 0; v < zg_mma.size(); ++v) zg_mma[v] = int(v);
+    d.nzg = int(vg_col.size());
     d.nzg_mma = int(zg_mma.size());
+    d.npiece = npiece;
+    d.nzsplit = int(zs_g.size());
     // ---- uploads
     TRY(upload(h, &d.bl_first, S.bl_first));
     TRY(upload(h, &d.bl_rptr, S.bl_rptr));
@@ -837,6 +862,11 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     TRY(upload(h, &d.zg_rows, zg_rows));
     TRY(upload(h, &d.zg_slot, zg_slot));
     TRY(upload(h, &d.zg_mma, zg_mma));
+    TRY(upload(h, &d.zg_col, vg_col));
+    TRY(upload(h, &d.zg_piece, vg_piece));
+    TRY(upload(h, &d.zs_g, zs_g));
+    TRY(upload(h, &d.zs_ptr, zs_ptr));
+    if (d.npiece > 0) TRY(dalloc(h, &d.zpart, size_t(d.npiece) * 32 * size_t(n)));
     TRY(upload(h, &d.pos, S.pos));
     if (d.cc) {
         TRY(upload(h, &d.ccol, ccol));

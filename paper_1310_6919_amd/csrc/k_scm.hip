@@ -143,13 +143,15 @@ typedef double d4 __attribute__((ext_vector_type(4)));   // one MFMA accumulator
 template <bool RHS>
 __global__ void __launch_bounds__(256)
 k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_ptr, const int *__restrict__ zg_rows,
-         const int *__restrict__ zg_slot, const double *__restrict__ Mvec, const double *__restrict__ Xh,
-         const double *__restrict__ Yi, double *__restrict__ out) {
+         const int *__restrict__ zg_slot, const int *__restrict__ zg_col, const int *__restrict__ zg_piece,
+         const double *__restrict__ Mvec, const double *__restrict__ Xh, const double *__restrict__ Yi,
+         double *__restrict__ out, double *__restrict__ zpart) {
     __shared__ double Mb[kZmRows * 33];
     __shared__ int Ur[kZmRows];
-    const int g = groups[blockIdx.y];
-    const int64_t u0 = zg_ptr[g];
-    const int K = int(zg_ptr[g + 1] - u0);   // a multiple of 4
+    const int vg = groups[blockIdx.y];   // a group or a piece of one
+    const int g = zg_col[vg];            // its columns 32 g ..
+    const int64_t u0 = zg_ptr[vg];
+    const int K = int(zg_ptr[vg + 1] - u0);   // a multiple of 4
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
     const int p = 64 * blockIdx.x + 16 * wv + li;
     const int pc = min(p, n - 1);   // clamped: loads stay in range
@@ -185,15 +187,38 @@ k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_p
             }
         sacc += __shfl_xor(sacc, 16);
         sacc += __shfl_xor(sacc, 32);
-        if (lk == 0 && p < n) out[int64_t(g) * n + p] = sacc;
+        if (lk == 0 && p < n) out[int64_t(vg) * n + p] = sacc;
     } else {
+        const int piece = zg_piece[vg];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = 32 * g + 16 * t + 4 * r + lk;
-                if (p < n && c < n) out[p + int64_t(n) * c] = acc[t][r];
+                if (p < n && c < n) {
+                    if (piece < 0)
+                        out[p + int64_t(n) * c] = acc[t][r];
+                    else
+                        zpart[(int64_t(piece) * 32 + (c - 32 * g)) * n + p] = acc[t][r];
+                }
             }
+    }
+}
+
+// Z(p, 32 g + cc) = the sum of the pieces' products in piece order, for the column
+// groups that were cut (blockIdx.y)
+__global__ void __launch_bounds__(256)
+k_zm_reduce(int n, const int *__restrict__ zs_g, const int *__restrict__ zs_ptr, const double *__restrict__ zpart,
+            double *__restrict__ Z) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = zs_g[blockIdx.y];
+    if (p >= n) return;
+    for (int cc = 0; cc < 32; ++cc) {
+        const int c = 32 * g + cc;
+        if (c >= n) break;
+        double s = 0.0;
+        for (int q = zs_ptr[blockIdx.y]; q < zs_ptr[blockIdx.y + 1]; ++q) s += zpart[(int64_t(q) * 32 + cc) * n + p];
+        Z[p + int64_t(n) * c] = s;
     }
 }
 
@@ -349,7 +374,11 @@ void launch_scm_general(const DevStruct &d, const int64_t *kq_ptr_host, const do
 void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, double *Z, hipStream_t st) {
     if (d.nzg_mma > 0)
         hipLaunchKernelGGL(k_zm_mma<false>, dim3((d.n + 63) / 64, d.nzg_mma), dim3(256), 0, st, d.n, d.zg_mma,
-                           d.zg_ptr, d.zg_rows, d.zg_slot, Mvec, Xh, (const double *)nullptr, Z);
+                           d.zg_ptr, d.zg_rows, d.zg_slot, d.zg_col, d.zg_piece, Mvec, Xh, (const double *)nullptr,
+                           Z, d.zpart);
+    if (d.nzsplit > 0)
+        hipLaunchKernelGGL(k_zm_reduce, dim3((d.n + 255) / 256, d.nzsplit), dim3(256), 0, st, d.n, d.zs_g, d.zs_ptr,
+                           (const double *)d.zpart, Z);
 }
 
 int rhs_had_parts(const DevStruct &d) { return d.nzg; }
@@ -359,7 +388,8 @@ void launch_rhs_hadamard(const DevStruct &d, const double *Mvec, const double *X
     const int nparts = rhs_had_parts(d);
     if (d.nzg_mma > 0)
         hipLaunchKernelGGL(k_zm_mma<true>, dim3((d.n + 63) / 64, d.nzg_mma), dim3(256), 0, st, d.n, d.zg_mma,
-                           d.zg_ptr, d.zg_rows, d.zg_slot, Mvec, Xh, Yi, part);
+                           d.zg_ptr, d.zg_rows, d.zg_slot, d.zg_col, d.zg_piece, Mvec, Xh, Yi, part,
+                           (double *)nullptr);
     hipLaunchKernelGGL(k_sum_partials, dim3((d.m + 63) / 64), dim3(256), 0, st, d.m, nparts,
                        (const double *)part, d.had_pos, hcol);
 }

@@ -126,12 +126,23 @@ struct DevStruct {
     // group (padded to a multiple of 4) and, per union row and column of the group, the
     // slot of the entry (-1: none); every group is a dense product on the MFMA over its
     // union, kZmRows union rows at a time.
-    int nzg = 0;                        // ceil(n / 32)
+    // A group whose union exceeds kZmSplit rows is cut into pieces of kZmPiece union
+    // rows, each a group of its own (split K): zg_col gives a group's columns (32 zg_col
+    // ..), zg_piece its piece (-1: a whole group).  The products of the pieces go to
+    // zpart (npiece x 32 x n) and are added in piece order into Z; the right-hand-side
+    // form simply has one partial sum per group.
+    int nzg = 0;                        // groups, pieces counted one by one
     const int64_t *zg_ptr = nullptr;    // nzg + 1: offsets into zg_rows (zg_slot: 32 per row)
     const int *zg_rows = nullptr;
     const int *zg_slot = nullptr;
+    const int *zg_col = nullptr;        // nzg
+    const int *zg_piece = nullptr;      // nzg
     int nzg_mma = 0;
     const int *zg_mma = nullptr;        // groups on the MFMA path
+    int npiece = 0, nzsplit = 0;        // pieces; column groups that were cut
+    const int *zs_g = nullptr;          // nzsplit: the column group
+    const int *zs_ptr = nullptr;        // nzsplit + 1: its pieces
+    double *zpart = nullptr;            // npiece x 32 x n work
     // general path, column-compressed form (k_scm_cc.hip): A_q = U_q + U_q^T + D_q with
     // U_q the strict triangle (upper or lower, whichever has the smaller column union C
     // over all q) and D_q the diagonal
@@ -152,6 +163,7 @@ struct DevStruct {
     int solve_generic = 0;              // 1: the substitutions always take the generic walk
 };
 constexpr int kZmRows = 128;
+constexpr int kZmSplit = 512, kZmPiece = 128;
 
 // ---- assembly and vectors (k_vec.hip)
 // out[s] = sum_t asm_val[t] * coef_k  + c1 * in1[s]; coef_0 = a0, coef_k = -y[k-1]
