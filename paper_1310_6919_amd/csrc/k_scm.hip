@@ -206,20 +206,16 @@ k_zm_mma(int n, const int *__restrict__ groups, const int64_t *__restrict__ zg_p
 }
 
 // Z(p, 32 g + cc) = the sum of the pieces' products in piece order, for the column
-// groups that were cut (blockIdx.y)
+// groups that were cut (blockIdx.y) and their columns cc (blockIdx.z)
 __global__ void __launch_bounds__(256)
 k_zm_reduce(int n, const int *__restrict__ zs_g, const int *__restrict__ zs_ptr, const double *__restrict__ zpart,
             double *__restrict__ Z) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = zs_g[blockIdx.y];
-    if (p >= n) return;
-    for (int cc = 0; cc < 32; ++cc) {
-        const int c = 32 * g + cc;
-        if (c >= n) break;
-        double s = 0.0;
-        for (int q = zs_ptr[blockIdx.y]; q < zs_ptr[blockIdx.y + 1]; ++q) s += zpart[(int64_t(q) * 32 + cc) * n + p];
-        Z[p + int64_t(n) * c] = s;
-    }
+    const int cc = blockIdx.z, c = 32 * zs_g[blockIdx.y] + cc;
+    if (p >= n || c >= n) return;
+    double s = 0.0;
+    for (int q = zs_ptr[blockIdx.y]; q < zs_ptr[blockIdx.y + 1]; ++q) s += zpart[(int64_t(q) * 32 + cc) * n + p];
+    Z[p + int64_t(n) * c] = s;
 }
 
 // out[k] = sum over the parts of part[c n + pos[k]] (pos maps constraint k to its
@@ -377,7 +373,7 @@ void launch_zcol(const DevStruct &d, const double *Xh, const double *Mvec, doubl
                            d.zg_ptr, d.zg_rows, d.zg_slot, d.zg_col, d.zg_piece, Mvec, Xh, (const double *)nullptr,
                            Z, d.zpart);
     if (d.nzsplit > 0)
-        hipLaunchKernelGGL(k_zm_reduce, dim3((d.n + 255) / 256, d.nzsplit), dim3(256), 0, st, d.n, d.zs_g, d.zs_ptr,
+        hipLaunchKernelGGL(k_zm_reduce, dim3((d.n + 255) / 256, d.nzsplit, 32), dim3(256), 0, st, d.n, d.zs_g, d.zs_ptr,
                            (const double *)d.zpart, Z);
 }
 
