@@ -227,9 +227,11 @@ def test_scm_rejects_non_pd():
 
 
 # ----------------------------------------------------------------- one PDIPM iteration
-@pytest.mark.parametrize("name", ["cfg1", "band_ragged", "normmin", "random_sdp"])
+@pytest.mark.parametrize("name", ["cfg1", "band_ragged", "normmin", "random_sdp", "normmin_split"])
 def test_iteration_matches_oracle(name):
-    prob = CASES[name]()
+    """normmin_split: the column group holding the arrow's dense columns has a row union
+    of 610 rows, more than the 512 above which the products X^ M are cut into pieces."""
+    prob = sdpgen.normmin(600, 10, 8, 0) if name == "normmin_split" else CASES[name]()
     rng = np.random.default_rng(21)
     Xfull, Y = _state(prob, rng)
     z = rng.standard_normal(prob.m) * 0.1
