@@ -644,6 +644,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
     std::vector<int> ccol, ds_v, seg_q, seg_row, seg_col;
     std::vector<int64_t> seg_ptr(1, 0);
     std::vector<double> ucat, dmat, seg_val;
+    std::vector<int> dq_few;
     if (!had && m > 0) {
         std::vector<uint8_t> in_up(n, 0), in_lo(n, 0), in_d(n, 0);
         for (int k = 1; k <= m; ++k)
@@ -698,6 +699,19 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
                 if (!full.empty()) seg_ptr.push_back(int64_t(seg_col.size()));
             }
             d.nseg = int64_t(seg_q.size());
+            {   // the constraints with a diagonal part, if few
+                std::vector<int> dq;
+                for (int q = 0; q < m; ++q)
+                    for (int64_t i = 0; i < nds; ++i)
+                        if (dmat[size_t(i) + size_t(nds) * q] != 0.0) {
+                            dq.push_back(q);
+                            break;
+                        }
+                if (int(dq.size()) <= kDqFew) {
+                    d.ndq = int(dq.size());
+                    dq_few.swap(dq);
+                }
+            }
         }
     }
     // aggregate pattern, full symmetric CSC with slots
@@ -873,6 +887,7 @@ static sdpc_status create_impl(const sdpc_problem *prob, const sdpc_params *para
         TRY(upload(h, &d.ucat, ucat));
         TRY(upload(h, &d.ds, ds_v));
         TRY(upload(h, &d.dmat, dmat));
+        TRY(upload(h, &d.dq, dq_few));
         TRY(upload(h, &d.seg_q, seg_q));
         TRY(upload(h, &d.seg_row, seg_row));
         TRY(upload(h, &d.seg_ptr, seg_ptr));

@@ -245,6 +245,37 @@ k_had_ds(int n, int nds, const int *__restrict__ ds, const double *__restrict__ 
     }
 }
 
+// diagT(a, q) = sum_i (X^ o Y^{-1})(ds_i, ds_a) D_q(ds_i) for the ndq constraints dq[] that
+// have a diagonal part (when they are few; the other columns of diagT are zeroed
+// beforehand): one wave per a reads column ds_a of X^ and Y^{-1} once (both are
+// symmetric), its lanes' sums added in a fixed order
+__global__ void __launch_bounds__(256)
+k_diag_few(int n, int nds, const int *__restrict__ ds, const double *__restrict__ Xh, const double *__restrict__ Yi,
+           const double *__restrict__ dmat, int ndq, const int *__restrict__ dq, double *__restrict__ diagT) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < nds; a += waves) {
+        const int64_t ca = int64_t(n) * ds[a];
+        double acc[kDqFew];
+#pragma unroll
+        for (int t = 0; t < kDqFew; ++t) acc[t] = 0.0;
+        for (int i = lane; i < nds; i += 64) {
+            const int64_t src = ds[i] + ca;
+            const double hv = Xh[src] * Yi[src];
+#pragma unroll
+            for (int t = 0; t < kDqFew; ++t)
+                if (t < ndq) acc[t] = fma(hv, dmat[i + int64_t(nds) * dq[t]], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kDqFew; ++t) {
+            if (t >= ndq) break;
+            double v = acc[t];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) diagT[a + int64_t(nds) * dq[t]] = v;
+        }
+    }
+}
+
 // diagT(a, q) += sum_c P_q(ds_a, c) Y^{-1}(ds_a, C_c) + sum_c P'_q(ds_a, c) X^(ds_a, C_c)
 // for q < nq (diagT: nds x nq column-major, already holding the D_q part)
 __global__ void __launch_bounds__(256)
@@ -372,11 +403,20 @@ void launch_scm_cc(const DevStruct &d, const double *Xh, const double *Yi, doubl
                            (const double *)nullptr, 0, w.YC, w.XC, w.Q, w.Qp);
     }
     if (nds > 0) {
-        // diagT(., q) = (X^ o Y^{-1})(Ds, Ds) D_q, then the U_q terms
-        hipLaunchKernelGGL(k_had_ds, dim3(grid_for(int64_t(nds) * nds, 256)), dim3(256), 0, st, n, nds, d.ds, Xh, Yi,
-                           H);
-        hipLaunchKernelGGL(k_gemm_nn, dim3((nds + 63) / 64, (m + 63) / 64, 1), dim3(256), 0, st, nds, m, nds, H, H,
-                           int64_t(nds), d.dmat, int64_t(nds), w.diagT, w.diagT, int64_t(nds));
+        // diagT(., q) = (X^ o Y^{-1})(Ds, Ds) D_q, then the U_q terms; with few D_q
+        // nonzero, one pass over the columns Ds of X^ and Y^{-1} instead of the product
+        if (d.ndq >= 0) {
+            hipLaunchKernelGGL(k_zero, dim3(grid_for(int64_t(nds) * m, 256)), dim3(256), 0, st, int64_t(nds) * m,
+                               w.diagT);
+            if (d.ndq > 0)
+                hipLaunchKernelGGL(k_diag_few, dim3(grid_for(nds, 4)), dim3(256), 0, st, n, nds, d.ds, Xh, Yi,
+                                   d.dmat, d.ndq, d.dq, w.diagT);
+        } else {
+            hipLaunchKernelGGL(k_had_ds, dim3(grid_for(int64_t(nds) * nds, 256)), dim3(256), 0, st, n, nds, d.ds, Xh,
+                               Yi, H);
+            hipLaunchKernelGGL(k_gemm_nn, dim3((nds + 63) / 64, (m + 63) / 64, 1), dim3(256), 0, st, nds, m, nds, H,
+                               H, int64_t(nds), d.dmat, int64_t(nds), w.diagT, w.diagT, int64_t(nds));
+        }
         if (nc > 0)
             hipLaunchKernelGGL(k_cc_diag, dim3(grid_for(int64_t(nds) * m, 256)), dim3(256), 0, st, n, nc, nds, m, d.ds,
                                w.P, w.Pp, w.YC, w.XC, w.diagT);

@@ -153,6 +153,10 @@ struct DevStruct {
     int nds = 0;                        // positions holding a diagonal entry of some A_q
     const int *ds = nullptr;            // nds
     const double *dmat = nullptr;       // nds x m column-major: D_q(ds[i])
+    // the constraints with a diagonal part when there are at most kDqFew of them (ndq
+    // of them, listed in dq), else ndq = -1
+    int ndq = -1;
+    const int *dq = nullptr;
     int64_t nseg = 0;                   // rows of A_1 .. A_m (full symmetric), in order
     const int *seg_q = nullptr;         // nseg
     const int *seg_row = nullptr;       // nseg
@@ -163,6 +167,7 @@ struct DevStruct {
     int solve_generic = 0;              // 1: the substitutions always take the generic walk
 };
 constexpr int kZmRows = 128;
+constexpr int kDqFew = 8;
 constexpr int kZmSplit = 512, kZmPiece = 128;
 
 // ---- assembly and vectors (k_vec.hip)
